@@ -1,0 +1,130 @@
+"""Pins of the oracle's backward geodesics in Kerr spacetime.
+
+- Constants of motion (energy E = -K_t, angular momentum L = K_phi, Carter
+  constant Q) and the null condition are conserved along every ray to the
+  integrator's truncation error, which falls by ~2^4 when eps halves
+  (classical fourth-order Runge-Kutta).
+- Schwarzschild: rays are captured iff the impact parameter is below
+  sqrt(27) M; the capture threshold found by bisection converges to it.
+- Kerr: a ray is captured iff the radial potential
+  R(r) = (r^2 + a^2 - a xi)^2 - Delta (eta + (xi - a)^2) has no root outside
+  the horizon (xi = L/E, eta = Q/E^2); the oracle agrees away from the
+  critical curve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_02733_amd import workloads as W
+
+
+def invariants(a, path):
+    out = []
+    for p in path:
+        r, th = p[0], p[1]
+        g = oracle.metric(a, 1.0, r, th)
+        K = p[3:7]
+        Kl = g @ K
+        E, L = -Kl[0], Kl[3]
+        Q = Kl[2] ** 2 + np.cos(th) ** 2 * (-a * a * E * E + L * L / np.sin(th) ** 2)
+        out.append((E, L, Q, (K @ g @ K) / K[0] ** 2))
+    return np.array(out)
+
+
+def max_drift(a, path):
+    inv = invariants(a, path)
+    E0, L0, Q0 = inv[0, :3]
+    scale = abs(E0) * (abs(L0) + 1.0)
+    return max(np.abs(inv[:, 0] - E0).max() / abs(E0), np.abs(inv[:, 1] - L0).max() / scale,
+               np.abs(inv[:, 2] - Q0).max() / (abs(Q0) + scale ** 2), np.abs(inv[:, 3]).max())
+
+
+@pytest.mark.parametrize("alpha,beta", [(9.0, 3.0), (-7.0, 6.0), (2.0, -11.0)])
+def test_constants_of_motion_conserved_with_fourth_order_convergence(alpha, beta):
+    cam = W.adaf_camera(16)
+    a = cam["a"]
+    drifts = []
+    for eps in (0.02, 0.01):
+        cam["eps"] = eps
+        path, st = oracle.trace_ray(cam, alpha, beta)
+        assert st == oracle.ESCAPED
+        drifts.append(max_drift(a, path))
+    assert drifts[1] < 1e-7
+    ratio = drifts[0] / drifts[1]
+    assert 8.0 < ratio < 32.0, ratio
+
+
+def test_invariants_conserved_on_captured_ray_down_to_stop_radius():
+    cam = W.adaf_camera(16)
+    path, st = oracle.trace_ray(cam, 1.0, 0.5)
+    assert st == oracle.CAPTURED
+    assert path[-1, 0] < 1.05 * oracle.horizon(cam["a"])
+    assert path[-2, 0] >= 1.05 * oracle.horizon(cam["a"])
+    assert max_drift(cam["a"], path) < 1e-6
+
+
+def _impact_parameter(cam, alpha):
+    X, K, _ = oracle.camera_launch(cam, alpha, 0.0)
+    Kl = oracle.metric(cam["a"], 1.0, X[1], X[2]) @ K
+    return np.sqrt(Kl[2] ** 2 + Kl[3] ** 2 / np.sin(X[2]) ** 2) / (-Kl[0])
+
+
+def _capture_threshold(cam):
+    lo, hi = 4.0, 7.0   # captured at lo, escapes at hi
+    assert oracle.trace_ray(cam, lo, 0.0)[1] == oracle.CAPTURED
+    assert oracle.trace_ray(cam, hi, 0.0)[1] == oracle.ESCAPED
+    for _ in range(36):
+        mid = 0.5 * (lo + hi)
+        if oracle.trace_ray(cam, mid, 0.0)[1] == oracle.CAPTURED:
+            lo = mid
+        else:
+            hi = mid
+    return _impact_parameter(cam, 0.5 * (lo + hi))
+
+
+def test_schwarzschild_capture_threshold_is_sqrt27():
+    cam = W.adaf_camera(16, a=0.0, incl_deg=90.0)
+    errs = []
+    for eps in (0.04, 0.02):
+        cam["eps"] = eps
+        errs.append(abs(_capture_threshold(cam) - np.sqrt(27.0)))
+    assert errs[1] < 1e-4
+    assert errs[1] < errs[0]
+
+
+def _kerr_captured(a, xi, eta):
+    c = eta + (xi - a) ** 2
+    A = a * a - a * xi
+    roots = np.roots([1.0, 0.0, 2 * A - c, 2 * c, A * A - a * a * c])
+    rh = 1 + np.sqrt(1 - a * a)
+    real = roots[np.abs(roots.imag) < 1e-9 * np.abs(roots).max()].real
+    return not np.any(real > rh)
+
+
+def test_kerr_capture_matches_radial_potential():
+    n = 20
+    cam = W.adaf_camera(n, jitter=0, fov=16.0)
+    a = cam["a"]
+    _, status, _ = oracle.render(cam, W.UNITS, W.ADAF)
+    agree = total = 0
+    for j in range(n):
+        for i in range(n):
+            al, be = oracle.pixel_position(cam, i, j)
+            X, K, _ = oracle.camera_launch(cam, al, be)
+            Kl = oracle.metric(a, 1.0, X[1], X[2]) @ K
+            E, L = -Kl[0], Kl[3]
+            Q = Kl[2] ** 2 + np.cos(X[2]) ** 2 * (-a * a * E * E + L * L / np.sin(X[2]) ** 2)
+            xi, eta = L / E, Q / E ** 2
+            expect = _kerr_captured(a, xi, eta)
+            # skip rays whose classification flips under a 1e-4 relative change
+            robust = all(_kerr_captured(a, xi * (1 + s), eta * (1 + t)) == expect
+                         for s in (-1e-4, 1e-4) for t in (-1e-4, 1e-4))
+            if not robust:
+                continue
+            total += 1
+            got = status[j, i] == oracle.CAPTURED
+            assert status[j, i] in (oracle.CAPTURED, oracle.ESCAPED)
+            agree += int(got == expect)
+    assert total > 0.9 * n * n
+    assert agree == total
+    assert 0 < (status == oracle.CAPTURED).sum() < n * n
