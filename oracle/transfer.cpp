@@ -17,7 +17,8 @@
  *    (I = N11 + N22, Q = N11 - N22, U = 2 Re N12, V = -2 Im N12), apply the
  *    exact constant-coefficient solution of dS/dlam = J - K S over w_n,
  *    rebuild N from S on the same legs;
- *  - fluid tetrad: e0 = u, e3 = (K + (K.u) u)/(-K.u), e2 along the part of b
+ *  - fluid tetrad: e0 = u, e3 = unit vector along K + (K.u) u (equal to
+ *    (K + (K.u) u)/(-K.u) for null K), e2 along the part of b
  *    orthogonal to u and e3 (fallback d_theta, then d_r), e1 completing a
  *    right-handed tetrad (det[e0, e1, e2, e3] > 0 in Kerr-Schild components);
  *  - invariant coefficients: J = (L/nu_obs) j/nu^2, A = (L/nu_obs) nu alpha,
@@ -98,10 +99,16 @@ struct FluidFrame {
 
 static void fluid_frame(const Mat4 g, const double u[4], const double K[4], const double b[4],
                         FluidFrame* F) {
+    /* e3: unit spatial direction of K in the fluid frame.  For an exactly null
+     * K this is (K + (K.u) u)/(-K.u); normalising explicitly keeps the tetrad
+     * orthonormal when the stored K carries the integrator's null drift. */
     double Ku = dot(g, K, u);
+    double v3[4];
+    for (int mu = 0; mu < 4; ++mu) v3[mu] = K[mu] + Ku * u[mu];
+    double n3 = std::sqrt(dot(g, v3, v3));
     for (int mu = 0; mu < 4; ++mu) {
         F->e0[mu] = u[mu];
-        F->e3[mu] = (K[mu] + Ku * u[mu]) / (-Ku);
+        F->e3[mu] = v3[mu] / n3;
     }
     const double* l3[1] = {F->e3};
     /* e2: along the field's part transverse to u and e3 */
