@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark of the polarized Kerr ray tracer on one MI355X.
+
+One step = one pass of the whole hot path over one image: per pixel camera
+launch, backward FP64 geodesic (stored), forward FP64 polarized transfer,
+camera projection, then the image reduction to total fluxes.  The workload is
+the analytic ADAF seen at 60 degrees at 230 GHz (1024 x 1024 by default,
+4096 x 4096 with --workload adaf4096), synthetic and seeded.
+
+Prints one JSON line with the throughput (rays/s), the roofline position of
+the dominant kernel and the CPU oracle's throughput on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# FP64 operations per ray-step of the wave-synchronous tracer (one geodesic
+# RK4 step plus one transfer point), FMA counted as two: measured with the
+# rocprofv3 FP64 VALU instruction counters on a divergence-free launch
+# (bench.py --flop-probe, every lane tracing the same ray), 64 lanes per wave
+# instruction.  See the design doc (measurement).
+FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "0")) or None
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
+HBM_PEAK_GBS = 8000.0
+
+
+def run_probe(kind):
+    import torch
+    from paper_2302_02733_amd import krt
+    from paper_2302_02733_amd import workloads as W
+    if kind == "copy":
+        n = 1 << 27  # 1 GiB of doubles
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        b = a.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read": n * 8, "bytes_written": n * 8}))
+        del b
+        return
+    cam = W.adaf_camera(256, jitter=0, fov=1e-9)
+    with krt.Context(0) as ctx:
+        ctx.set_units(W.UNITS)
+        ctx.set_model(W.ADAF)
+        out = ctx.trace(cam)
+    print(json.dumps({"probe": "flop", "rays": out["stats"]["rays"],
+                      "total_steps": out["stats"]["total_steps"],
+                      "kernel_ms": out["stats"]["kernel_ms"]}))
+
+
+def cpu_baseline(w, sample):
+    import numpy as np
+    import oracle
+    from paper_2302_02733_amd import workloads as W
+    cam = w["camera"]
+    pix = W.pixel_sample(cam["nx"], cam["ny"], sample, 7)
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    S, st, ns = oracle.render(cam, w["units"], w["model"], pixels=pix, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": len(pix) / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pix)} seeded pixels (seed 7) of the {cam['nx']}x{cam['ny']} image, "
+                      f"{int(np.sum(ns))} ray-steps, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="adaf1024", choices=["adaf64", "adaf1024", "adaf4096"])
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="pixels for the oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--flop-probe", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the path has no multi-GPU mode); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    if args.flop_probe or args.copy_probe:
+        run_probe("flop" if args.flop_probe else "copy")
+        return
+
+    import torch
+    from paper_2302_02733_amd import krt
+    from paper_2302_02733_amd import workloads as W
+
+    w = W.workload(args.workload)
+    cam = w["camera"]
+    npix = cam["nx"] * cam["ny"]
+    dev = torch.device("cuda", 0)
+    stokes = torch.empty((4, cam["ny"], cam["nx"]), dtype=torch.float64, device=dev)
+    status = torch.empty((cam["ny"], cam["nx"]), dtype=torch.uint8, device=dev)
+    with krt.Context(0) as ctx:
+        ctx.set_units(w["units"])
+        ctx.set_model(w["model"])
+        for _ in range(args.warmup):
+            ctx.trace(cam, stokes=stokes, status=status)
+            ctx.reduce(stokes, cam)
+            print(f"warmup step done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms, steps, flux = [], [], None
+        for k in range(args.steps):
+            out = ctx.trace(cam, stokes=stokes, status=status)
+            flux, imax = ctx.reduce(stokes, cam)
+            kms.append(out["stats"]["kernel_ms"][0])
+            steps.append(out["stats"]["total_steps"])
+            print(f"step {k} done: {out['stats']['kernel_ms'][0]:.1f} ms in the tracer", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stats = out["stats"]
+
+    ms_per_step = 1e3 * dt / args.steps
+    kernel_ms = sum(kms) / len(kms)
+    ray_steps = sum(steps) / len(steps)
+    if FLOPS_PER_RAY_STEP:
+        achieved = FLOPS_PER_RAY_STEP * ray_steps / (kernel_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "kernel": "trace_waves", "kernel_ms": kernel_ms,
+                "flops_per_ray_step": FLOPS_PER_RAY_STEP}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": None, "traffic": None, "kernel": "trace_waves", "kernel_ms": kernel_ms}
+    line = {
+        "metric": "polarized rays/s (FP64 geodesic + FP64 polarized transfer, whole image)",
+        "value": args.steps * npix / dt,
+        "unit": "rays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "model": "analytic ADAF (a=0.9375, 60 deg, 230 GHz)",
+                   "pixels": npix, "eps": cam["eps"], "max_steps": cam["max_steps"],
+                   "parallelism": "single GPU"},
+        "ray_steps_per_s": ray_steps / (ms_per_step * 1e-3),
+        "mean_steps_per_ray": ray_steps / npix,
+        "long_rays": stats["long_rays"],
+        "flux_jy": flux,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * krt: polarized Kerr ray tracing on AMD MI355X (gfx950) -- C ABI.
+ *
+ * The library implements the hot path of the method of Moscibrodzka &
+ * Yfantis (2023, "Prospects for ray-tracing light intensity and polarization
+ * in models of accreting compact objects using a GPU"), Sec. 2.1-2.2: one ray
+ * per camera pixel; a null geodesic integrated backward in time from the
+ * camera with an adaptive step controlled by a parameter eps, and saved; then
+ * covariant, fully polarized synchrotron transfer (Stokes I, Q, U, V carried
+ * as a complex coherency matrix in the coordinate frame) integrated forward
+ * along the saved path toward the camera, with plasma quantities and
+ * emission / absorption / Faraday rotation and conversion coefficients
+ * evaluated at every stored point.  The product is one polarized image
+ * (Table 1 caption: Stokes I, Q, U, V per image).
+ *
+ * Conventions.  Geometry in units G = c = M = 1, Kerr-Schild coordinates
+ * (t, r, theta, phi); radiative quantities in cgs.  Pixel (i, j) of an
+ * nx x ny image sits at alpha = fov_x ((i + 1/2 + d_x)/nx - 1/2),
+ * beta = fov_y ((j + 1/2 + d_y)/ny - 1/2) (d = SplitMix64 jitter in
+ * [-1/2, 1/2) or 0); +alpha is image right (along e_phi of the static camera),
+ * +beta is image up (along -e_theta).
+ *
+ * Memory.  Every pointer named d_* is DEVICE memory owned by the caller
+ * (allocated e.g. by PyTorch on the context's device); the library never
+ * frees it.  The library owns the context and its scratch memory (path store,
+ * counters, tables), allocated by krt_create / krt_trace and freed by
+ * krt_destroy.  No managed memory is used.
+ *
+ * Streams.  Every call enqueues on the context's stream (default: the null
+ * stream; see krt_set_stream) and returns without waiting, except where a
+ * function says it synchronises.
+ *
+ * Errors.  Functions return KRT_OK or an error code; krt_last_error() gives
+ * a message.  All parameter checks run on the host before any launch.
+ * Numerical trouble on a single ray is not an error: it is reported per
+ * pixel in the status image (KRT_RAY_*) and counted in krt_stats.
+ */
+#ifndef KRT_H
+#define KRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KRT_ABI_VERSION 1
+
+typedef enum {
+    KRT_OK = 0,
+    KRT_E_INVAL = 1,       /* invalid argument (checked on the host)          */
+    KRT_E_NOMEM = 2,       /* device or host allocation failed                */
+    KRT_E_HIP = 3,         /* HIP runtime error                               */
+    KRT_E_STATE = 4,       /* call out of order (e.g. no model set)           */
+    KRT_E_UNSUPPORTED = 5  /* valid but not supported by this build           */
+} krt_status;
+
+/* Per-pixel ray status (uint8 status image). */
+enum {
+    KRT_RAY_ESCAPED = 0,   /* left through r > r_cam moving outward           */
+    KRT_RAY_CAPTURED = 1,  /* reached r < 1.05 r_+ (flat test mode: r < 1e-6) */
+    KRT_RAY_STEP_CAP = 2,  /* hit max_steps                                   */
+    KRT_RAY_NONFINITE = 3, /* non-finite state or Stokes vector               */
+    KRT_RAY_AXIS = 4       /* sin(theta) < 1e-12                              */
+};
+
+typedef struct krt_ctx krt_ctx;
+
+/* Camera and integration parameters.  Sec. 2.1 lists spin, viewing angle,
+ * observing frequency, field of view and resolution; Sec. 2.2 the step
+ * parameter eps.  Every struct starts with its size (set it to sizeof). */
+typedef struct {
+    uint32_t struct_size;
+    double a;            /* spin, |a| < 1                                     */
+    double incl_deg;     /* camera polar angle theta_o, 0 < theta_o < 180     */
+    double phi_deg;      /* camera azimuth                                    */
+    double r_cam;        /* camera radius (units of M), > 2 r_+               */
+    double fov_x, fov_y; /* field of view (units of M), > 0                   */
+    int32_t nx, ny;      /* resolution, >= 1                                  */
+    double freq_hz;      /* observing frequency at the camera, > 0            */
+    double eps;          /* step parameter, 0 < eps <= 0.5                    */
+    int32_t max_steps;   /* step cap per ray, >= 1                            */
+    int32_t jitter;      /* 1: seeded jitter inside each pixel, 0: centres    */
+    uint64_t seed;       /* jitter seed                                       */
+    int32_t mass_factor; /* 1: Kerr; 0: flat space (test mode)                */
+} krt_camera;
+
+/* Physical units: black-hole mass and distance (Sec. 2.1: the image
+ * normalisation depends on the mass-accretion-rate scale). */
+typedef struct {
+    uint32_t struct_size;
+    double M_bh_g;       /* g, > 0                                            */
+    double dist_cm;      /* cm, > 0                                           */
+} krt_units;
+
+/* Analytic ADAF-like flow (Sec. 2.1 semianalytic model; parameters are a
+ * reading: n_e = n0 r^-3/2 exp(-z^2/(2 (h r)^2)), z = r cos(theta),
+ * T_e = T0/r, |B| from beta = p_virial/p_mag with p_virial = n_e m_p c^2/(6 r),
+ * Keplerian rotation outside the ISCO and zero angular momentum inside,
+ * toroidal field). */
+typedef struct {
+    uint32_t struct_size;
+    double n0_cgs;       /* >= 0 */
+    double T0_K;         /* > 0  */
+    double beta;         /* > 0  */
+    double h_over_r;     /* > 0  */
+    int32_t field_geom;  /* 0: toroidal (the only value supported)            */
+} krt_adaf;
+
+/* Gridded GRMHD-like snapshot on a modified Kerr-Schild grid (Sec. 2.1:
+ * plasma read from precomputed 3D arrays and interpolated at every step).
+ * x1 = ln r, theta = pi x2 + (1 - hslope)/2 sin(2 pi x2), x3 = phi;
+ * cell-centred. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t n1, n2, n3;
+    double x1_start, dx1, x2_start, dx2, x3_start, dx3;
+    double hslope;
+    double gamma_ad;     /* adiabatic index                                   */
+    double M_unit_g;     /* mass unit: rho_unit = M_unit / L^3                */
+    double R_high, R_low;
+    double sigma_cut;    /* no emission where b.b/rho > sigma_cut             */
+    double r_emit_max;   /* no emission beyond this radius                    */
+    int32_t layout;      /* 0: [n1][n2][n3][8] (rho, u, U1..3, B1..3)         */
+} krt_snapshot_desc;
+
+/* Counters of one krt_trace call. */
+typedef struct {
+    uint32_t struct_size;
+    int64_t rays;            /* pixels traced                                 */
+    int64_t total_steps;     /* sum over rays of geodesic steps               */
+    int64_t status_count[5]; /* rays per KRT_RAY_* status                     */
+    int32_t max_steps_seen;  /* longest ray                                   */
+    int64_t long_rays;       /* rays longer than the fast path's store        */
+    double kernel_ms[2];     /* device time of the wave-synchronous tracer and
+                                of the long-ray tracer (HIP events)           */
+} krt_stats;
+
+/* ---- lifecycle ---- */
+
+/* Version of this ABI (KRT_ABI_VERSION). */
+int krt_abi_version(void);
+
+/* Creates a context on HIP device `device` (which becomes current for the
+ * calling thread) and builds the library's constant tables there.
+ * *out receives the context.  Errors: KRT_E_INVAL (bad device or NULL out),
+ * KRT_E_NOMEM, KRT_E_HIP. */
+krt_status krt_create(int device, krt_ctx** out);
+
+/* Waits for the context's stream, frees everything the context owns and the
+ * context itself.  NULL is accepted. */
+krt_status krt_destroy(krt_ctx* ctx);
+
+/* Borrows a hipStream_t for all later calls (NULL: the null stream).  The
+ * caller keeps ownership and must keep the stream alive. */
+krt_status krt_set_stream(krt_ctx* ctx, void* hip_stream);
+
+/* Sets the physical units (default: none; krt_trace needs them). */
+krt_status krt_set_units(krt_ctx* ctx, const krt_units* units);
+
+/* Selects the analytic ADAF model with these parameters. */
+krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* adaf);
+
+/* Selects the snapshot model.  d_prims (device memory, layout per desc,
+ * dtype 0 = FP64) is borrowed until the model is replaced or the context is
+ * destroyed; the caller must keep it alive and unchanged meanwhile. */
+krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc,
+                                  const void* d_prims, int dtype);
+
+/* ---- the hot path ---- */
+
+/* Traces the whole image: per pixel, camera launch, backward geodesic (stored),
+ * forward polarized transfer.  d_stokes: [4][ny][nx] FP64, Stokes I, Q, U, V
+ * in erg s^-1 cm^-2 sr^-1 Hz^-1 at the camera.  d_status: [ny][nx] uint8
+ * KRT_RAY_* (may be NULL).  Asynchronous; when out_stats is non-NULL the call
+ * synchronises the stream and fills it.  Errors: KRT_E_INVAL, KRT_E_STATE
+ * (no units or model), KRT_E_NOMEM, KRT_E_HIP. */
+krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
+                     krt_stats* out_stats);
+
+/* As krt_trace, and also writes the number of geodesic steps of every ray to
+ * d_nsteps ([ny][nx] int32, may be NULL). */
+krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes,
+                           uint8_t* d_status, int32_t* d_nsteps, krt_stats* out_stats);
+
+/* Image reduction: total flux densities F_S = 1e23 dOmega sum_ij S_ij in Jy,
+ * dOmega = (fov_x L / (nx D)) (fov_y L / (ny D)), L = G M / c^2, with
+ * compensated summation, and the maximum of Stokes I.  d_stokes as written by
+ * krt_trace for the same camera.  Synchronises the stream.  Errors:
+ * KRT_E_INVAL, KRT_E_STATE (no units), KRT_E_HIP. */
+krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam,
+                      double out_flux_jy[4], double* out_imax);
+
+/* Message of the last error on this context (never NULL). */
+const char* krt_last_error(const krt_ctx* ctx);
+
+/* ---- host-only checks (no device needed) ---- */
+
+/* Validates a camera without a context: KRT_OK or KRT_E_INVAL with a message
+ * copied into msg (msg_len bytes, may be 0). */
+krt_status krt_check_camera(const krt_camera* cam, char* msg, size_t msg_len);
+
+/* ---- component hooks (same ABI; used by the parity tests) ---- */
+
+/* Geodesic phase only, for every pixel: d_end_state [ny][nx][8] receives the
+ * last stored point (r, theta, phi, K^t, K^r, K^theta, K^phi, dlam),
+ * d_nsteps [ny][nx] the step count, d_status [ny][nx] the status. */
+krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_state,
+                             int32_t* d_nsteps, uint8_t* d_status);
+
+/* Plasma of the current model at n points: d_X [n][3] = (r, theta, phi) with
+ * spin a and mass factor m; d_out [n][12] = (n_e, Theta_e, B, u^0..3, b^0..3,
+ * valid).  Needs units for the snapshot model. */
+krt_status krt_plasma_eval(krt_ctx* ctx, int64_t n, double a, int32_t mass_factor,
+                           const double* d_X, double* d_out);
+
+/* Fluid-frame thermal coefficients at n points: d_in [n][5] = (n_e, Theta_e,
+ * B, nu, cos theta_B); d_out [n][8] = (j_I, j_Q, j_V, alpha_I, alpha_Q,
+ * alpha_V, rho_Q, rho_V), cgs. */
+krt_status krt_coeffs(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out);
+
+/* Bessel-function ratios at n arguments: d_out [n][2] = (K0/K2, K1/K2). */
+krt_status krt_bessel_ratios(krt_ctx* ctx, int64_t n, const double* d_x, double* d_out);
+
+/* Constant-coefficient polarized update over w at n points, for thermal
+ * (Kirchhoff) coefficients: d_coef [n][6] = (S_eq, A_I, A_Q, A_V, R_Q, R_V),
+ * so that the emission is J = S_eq (A_I, A_Q, 0, A_V); d_S [n][4] in,
+ * d_out [n][4] out. */
+krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S,
+                            double w, double* d_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

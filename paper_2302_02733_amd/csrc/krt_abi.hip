@@ -1,0 +1,509 @@
+// C ABI of the polarized Kerr ray tracer (see include/krt.h): host-side
+// validation, context and scratch management, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "krt.h"
+#include "krt_kernels.hpp"
+
+using namespace krt;
+
+struct krt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    bool units_set = false;
+    krt_units units{};
+    int model = -1;
+    krt_adaf adaf{};
+    double* btab = nullptr;
+    // wave-synchronous path store
+    double* pool = nullptr;
+    size_t pool_bytes = 0;
+    int pool_cap = 0;
+    int pool_blocks = 0;
+    // long-ray store
+    double* long_pool = nullptr;
+    size_t long_bytes = 0;
+    int long_slots = 0;
+    int long_max_steps = -1;
+    int32_t* overflow_list = nullptr;
+    size_t overflow_cap = 0;
+    // counters: [0] tile queue, [1] overflow count (unsigned); then 8 x u64
+    unsigned* work = nullptr;
+    double* red_partial = nullptr;
+    double* host_buf = nullptr;  // pinned, 16 doubles
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+constexpr int kWorkWords = 2 + 2 * 8;
+constexpr int kRedBlocks = 1024;
+
+krt_status fail(krt_ctx* ctx, krt_status code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+krt_status hip_fail(krt_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, KRT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define KRT_HIP(ctx, call)                                          \
+    do {                                                            \
+        hipError_t e_ = (call);                                     \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);    \
+    } while (0)
+
+bool finite_all(std::initializer_list<double> v) {
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+double horizon(double a, double m) { return m == 0.0 ? 0.0 : m + std::sqrt(m * m - a * a); }
+
+// r_isco of Kerr (Bardeen, Press & Teukolsky 1972), prograde for a > 0.
+double isco(double a) {
+    const double aa = std::fabs(a);
+    const double z1 = 1.0 + std::cbrt(1.0 - aa * aa) * (std::cbrt(1.0 + aa) + std::cbrt(1.0 - aa));
+    const double z2 = std::sqrt(3.0 * aa * aa + z1 * z1);
+    return 3.0 + z2 - (a >= 0.0 ? 1.0 : -1.0) * std::sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
+}
+
+std::string check_camera(const krt_camera* c) {
+    if (!c) return "camera is NULL";
+    if (c->struct_size != sizeof(krt_camera)) return "camera struct_size mismatch";
+    if (!finite_all({c->a, c->incl_deg, c->phi_deg, c->r_cam, c->fov_x, c->fov_y, c->freq_hz, c->eps}))
+        return "camera has a non-finite field";
+    if (!(std::fabs(c->a) < 1.0)) return "spin must satisfy |a| < 1";
+    if (c->mass_factor != 0 && c->mass_factor != 1) return "mass_factor must be 0 or 1";
+    if (!(c->r_cam > 0.0) || !(c->r_cam > 2.0 * horizon(c->a, c->mass_factor)))
+        return "r_cam must exceed twice the horizon radius";
+    if (c->nx < 1 || c->ny < 1) return "nx and ny must be >= 1";
+    if ((int64_t)c->nx * c->ny > (int64_t)INT32_MAX / 2) return "image too large";
+    if (!(c->freq_hz > 0.0)) return "freq_hz must be > 0";
+    if (!(c->eps > 0.0 && c->eps <= 0.5)) return "eps must satisfy 0 < eps <= 0.5";
+    if (c->max_steps < 1) return "max_steps must be >= 1";
+    if (!(c->incl_deg > 0.0 && c->incl_deg < 180.0)) return "incl_deg must be in (0, 180)";
+    if (!(c->fov_x > 0.0 && c->fov_y > 0.0)) return "field of view must be > 0";
+    if (c->jitter != 0 && c->jitter != 1) return "jitter must be 0 or 1";
+    return "";
+}
+
+CameraDesc camera_desc(const krt_camera* c) {
+    CameraDesc d;
+    d.a = c->a;
+    d.m = (double)c->mass_factor;
+    d.r_cam = c->r_cam;
+    d.th = c->incl_deg * kPi / 180.0;
+    d.ph = c->phi_deg * kPi / 180.0;
+    d.fov_x = c->fov_x;
+    d.fov_y = c->fov_y;
+    d.freq = c->freq_hz;
+    d.nx = c->nx;
+    d.ny = c->ny;
+    d.jitter = c->jitter;
+    d.seed = c->seed;
+    return d;
+}
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v ? std::atoi(v) : dflt;
+}
+
+TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
+    TraceArgs A;
+    std::memset(&A, 0, sizeof(A));
+    A.cam = camera_desc(cam);
+    A.eps = cam->eps;
+    A.r_stop = cam->mass_factor == 0 ? 1e-6 : 1.05 * horizon(cam->a, 1.0);
+    A.L_cm = ctx->units_set ? kG * ctx->units.M_bh_g / (kC * kC) : 0.0;
+    A.max_steps = cam->max_steps;
+    A.model = kModelAdaf;
+    A.adaf.n0 = ctx->adaf.n0_cgs;
+    A.adaf.T0 = ctx->adaf.T0_K;
+    A.adaf.beta = ctx->adaf.beta;
+    A.adaf.h = ctx->adaf.h_over_r;
+    A.adaf.risco = isco(cam->a);
+    A.btab = ctx->btab;
+    A.tiles_x = (cam->nx + 7) / 8;
+    A.nbatch = A.tiles_x * ((cam->ny + 7) / 8);
+    A.queue = ctx->work;
+    A.overflow_count = ctx->work + 1;
+    A.counters = reinterpret_cast<unsigned long long*>(ctx->work + 2);
+    return A;
+}
+
+// Sizes the wave-synchronous store: one slice of `cap` points for every
+// wavefront of the persistent grid (as many blocks as fit on the device).
+krt_status ensure_pool(krt_ctx* ctx) {
+    const int cap = env_int("KRT_PATH_CAP", 4096);
+    const double budget_gb = (double)env_int("KRT_POOL_GB", 48);
+    int per_cu = 0;
+    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<false>, 256, 0));
+    if (per_cu < 1) per_cu = 1;
+    int blocks = per_cu * ctx->cu_count;
+    const size_t per_block = (size_t)4 * 64 * cap * 8 * sizeof(double);
+    const size_t budget = (size_t)(budget_gb * 1073741824.0);
+    if ((size_t)blocks * per_block > budget) blocks = (int)(budget / per_block);
+    if (blocks < 1) return fail(ctx, KRT_E_NOMEM, "path store budget too small");
+    const size_t need = (size_t)blocks * per_block;
+    if (ctx->pool && ctx->pool_cap == cap && ctx->pool_blocks == blocks) return KRT_OK;
+    if (ctx->pool) {
+        KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        KRT_HIP(ctx, hipFree(ctx->pool));
+        ctx->pool = nullptr;
+    }
+    if (hipMalloc(&ctx->pool, need) != hipSuccess) {
+        ctx->pool = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate the path store");
+    }
+    ctx->pool_bytes = need;
+    ctx->pool_cap = cap;
+    ctx->pool_blocks = blocks;
+    return KRT_OK;
+}
+
+krt_status ensure_long(krt_ctx* ctx, int max_steps, size_t npix) {
+    if (ctx->long_pool == nullptr || ctx->long_max_steps != max_steps) {
+        if (ctx->long_pool) {
+            KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            KRT_HIP(ctx, hipFree(ctx->long_pool));
+            ctx->long_pool = nullptr;
+        }
+        const size_t per = (size_t)(max_steps + 1) * 8 * sizeof(double);
+        int slots = 1024;
+        while (slots > 64 && (size_t)slots * per > ((size_t)4 << 30)) slots /= 2;
+        if (hipMalloc(&ctx->long_pool, (size_t)slots * per) != hipSuccess) {
+            ctx->long_pool = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, KRT_E_NOMEM, "cannot allocate the long-ray store");
+        }
+        ctx->long_slots = slots;
+        ctx->long_max_steps = max_steps;
+        ctx->long_bytes = (size_t)slots * per;
+    }
+    if (ctx->overflow_cap < npix) {
+        if (ctx->overflow_list) {
+            KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            KRT_HIP(ctx, hipFree(ctx->overflow_list));
+            ctx->overflow_list = nullptr;
+        }
+        if (hipMalloc(&ctx->overflow_list, npix * sizeof(int32_t)) != hipSuccess) {
+            ctx->overflow_list = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, KRT_E_NOMEM, "cannot allocate the overflow list");
+        }
+        ctx->overflow_cap = npix;
+    }
+    return KRT_OK;
+}
+
+krt_status fill_stats(krt_ctx* ctx, const krt_camera* cam, krt_stats* s) {
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, ctx->work + 2, 8 * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    const unsigned long long* c = reinterpret_cast<const unsigned long long*>(ctx->host_buf);
+    s->struct_size = sizeof(krt_stats);
+    s->rays = (int64_t)cam->nx * cam->ny;
+    s->total_steps = (int64_t)c[0];
+    for (int k = 0; k < 5; ++k) s->status_count[k] = (int64_t)c[1 + k];
+    s->max_steps_seen = (int32_t)c[6];
+    s->long_rays = (int64_t)c[7];
+    float t0 = 0.0f, t1 = 0.0f;
+    KRT_HIP(ctx, hipEventElapsedTime(&t0, ctx->ev[0], ctx->ev[1]));
+    KRT_HIP(ctx, hipEventElapsedTime(&t1, ctx->ev[1], ctx->ev[2]));
+    s->kernel_ms[0] = t0;
+    s->kernel_ms[1] = t1;
+    return KRT_OK;
+}
+
+krt_status check_ready(krt_ctx* ctx, const krt_camera* cam) {
+    if (!ctx) return KRT_E_INVAL;
+    const std::string m = check_camera(cam);
+    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
+    if (!ctx->units_set) return fail(ctx, KRT_E_STATE, "units not set");
+    if (ctx->model < 0) return fail(ctx, KRT_E_STATE, "no plasma model set");
+    return KRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int krt_abi_version(void) { return KRT_ABI_VERSION; }
+
+krt_status krt_check_camera(const krt_camera* cam, char* msg, size_t msg_len) {
+    const std::string m = check_camera(cam);
+    if (msg && msg_len > 0) {
+        std::strncpy(msg, m.c_str(), msg_len - 1);
+        msg[msg_len - 1] = '\0';
+    }
+    return m.empty() ? KRT_OK : KRT_E_INVAL;
+}
+
+krt_status krt_create(int device, krt_ctx** out) {
+    if (!out) return KRT_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return KRT_E_INVAL;
+    krt_ctx* ctx = new (std::nothrow) krt_ctx();
+    if (!ctx) return KRT_E_NOMEM;
+    ctx->device = device;
+    krt_status st = KRT_OK;
+    do {
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) { st = hip_fail(ctx, e, "hipSetDevice"); break; }
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, device);
+        if (e != hipSuccess) { st = hip_fail(ctx, e, "hipGetDeviceProperties"); break; }
+        ctx->cu_count = prop.multiProcessorCount;
+        if (hipMalloc(&ctx->work, kWorkWords * sizeof(unsigned)) != hipSuccess ||
+            hipMalloc(&ctx->red_partial, kRedBlocks * 9 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&ctx->btab, (size_t)kBesPanels * 2 * kBesCoef * sizeof(double)) != hipSuccess ||
+            hipHostMalloc(&ctx->host_buf, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreate(&ctx->ev[0]) != hipSuccess || hipEventCreate(&ctx->ev[1]) != hipSuccess ||
+            hipEventCreate(&ctx->ev[2]) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(ctx, KRT_E_NOMEM, "cannot allocate context buffers");
+            break;
+        }
+        // Bessel-ratio table: node values, then Chebyshev coefficients
+        double* vals = nullptr;
+        if (hipMalloc(&vals, (size_t)kBesPanels * kBesCoef * 2 * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(ctx, KRT_E_NOMEM, "cannot allocate table scratch");
+            break;
+        }
+        const int nn = kBesPanels * kBesCoef;
+        hipLaunchKernelGGL(bessel_table_nodes, dim3((nn + 127) / 128), dim3(128), 0, nullptr, vals);
+        const int nc = kBesPanels * 2 * kBesCoef;
+        hipLaunchKernelGGL(bessel_table_coefs, dim3((nc + 127) / 128), dim3(128), 0, nullptr, vals,
+                           ctx->btab);
+        e = hipDeviceSynchronize();
+        (void)hipFree(vals);
+        if (e != hipSuccess) { st = hip_fail(ctx, e, "bessel table"); break; }
+        e = hipGetLastError();
+        if (e != hipSuccess) { st = hip_fail(ctx, e, "bessel table launch"); break; }
+    } while (0);
+    if (st != KRT_OK) {
+        krt_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return KRT_OK;
+}
+
+krt_status krt_destroy(krt_ctx* ctx) {
+    if (!ctx) return KRT_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pool) (void)hipFree(ctx->pool);
+    if (ctx->long_pool) (void)hipFree(ctx->long_pool);
+    if (ctx->overflow_list) (void)hipFree(ctx->overflow_list);
+    if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->red_partial) (void)hipFree(ctx->red_partial);
+    if (ctx->btab) (void)hipFree(ctx->btab);
+    if (ctx->host_buf) (void)hipHostFree(ctx->host_buf);
+    for (int k = 0; k < 3; ++k)
+        if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
+    delete ctx;
+    return KRT_OK;
+}
+
+krt_status krt_set_stream(krt_ctx* ctx, void* hip_stream) {
+    if (!ctx) return KRT_E_INVAL;
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return KRT_OK;
+}
+
+krt_status krt_set_units(krt_ctx* ctx, const krt_units* u) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!u || u->struct_size != sizeof(krt_units)) return fail(ctx, KRT_E_INVAL, "bad units struct");
+    if (!(std::isfinite(u->M_bh_g) && u->M_bh_g > 0.0 && std::isfinite(u->dist_cm) && u->dist_cm > 0.0))
+        return fail(ctx, KRT_E_INVAL, "units must be finite and > 0");
+    ctx->units = *u;
+    ctx->units_set = true;
+    return KRT_OK;
+}
+
+krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* p) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!p || p->struct_size != sizeof(krt_adaf)) return fail(ctx, KRT_E_INVAL, "bad adaf struct");
+    if (!finite_all({p->n0_cgs, p->T0_K, p->beta, p->h_over_r}) || !(p->n0_cgs >= 0.0) ||
+        !(p->T0_K > 0.0) || !(p->beta > 0.0) || !(p->h_over_r > 0.0))
+        return fail(ctx, KRT_E_INVAL, "ADAF parameters must be finite, n0 >= 0, T0, beta, h > 0");
+    if (p->field_geom != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only toroidal fields (0) are supported");
+    ctx->adaf = *p;
+    ctx->model = kModelAdaf;
+    return KRT_OK;
+}
+
+krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, const void* d_prims,
+                                  int dtype) {
+    if (!ctx) return KRT_E_INVAL;
+    (void)desc;
+    (void)d_prims;
+    (void)dtype;
+    return fail(ctx, KRT_E_UNSUPPORTED, "snapshot model not available in this build");
+}
+
+krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
+                           int32_t* d_nsteps, krt_stats* out_stats) {
+    krt_status st = check_ready(ctx, cam);
+    if (st != KRT_OK) return st;
+    if (!d_stokes) return fail(ctx, KRT_E_INVAL, "d_stokes is NULL");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t npix = (size_t)cam->nx * cam->ny;
+    if ((st = ensure_pool(ctx)) != KRT_OK) return st;
+    if ((st = ensure_long(ctx, cam->max_steps, npix)) != KRT_OK) return st;
+    TraceArgs A = base_args(ctx, cam);
+    A.pool = ctx->pool;
+    A.cap = ctx->pool_cap;
+    A.long_pool = ctx->long_pool;
+    A.long_slots = ctx->long_slots;
+    A.overflow_list = ctx->overflow_list;
+    A.stokes = d_stokes;
+    A.status = d_status;
+    A.nsteps = d_nsteps;
+    KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
+    if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    hipLaunchKernelGGL(trace_waves<false>, dim3(ctx->pool_blocks), dim3(256), 0, ctx->stream, A);
+    KRT_HIP(ctx, hipGetLastError());
+    if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    hipLaunchKernelGGL(trace_long, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+    KRT_HIP(ctx, hipGetLastError());
+    if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    if (out_stats) return fill_stats(ctx, cam, out_stats);
+    return KRT_OK;
+}
+
+krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
+                     krt_stats* out_stats) {
+    return krt_trace_steps(ctx, cam, d_stokes, d_status, nullptr, out_stats);
+}
+
+krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_state,
+                             int32_t* d_nsteps, uint8_t* d_status) {
+    if (!ctx) return KRT_E_INVAL;
+    const std::string m = check_camera(cam);
+    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
+    if (!d_end_state) return fail(ctx, KRT_E_INVAL, "d_end_state is NULL");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    TraceArgs A = base_args(ctx, cam);
+    A.end_state = d_end_state;
+    A.nsteps = d_nsteps;
+    A.status = d_status;
+    int per_cu = 0;
+    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<true>, 256, 0));
+    const int blocks = (per_cu < 1 ? 1 : per_cu) * ctx->cu_count;
+    KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
+    hipLaunchKernelGGL(trace_waves<true>, dim3(blocks), dim3(256), 0, ctx->stream, A);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam, double out_flux_jy[4],
+                      double* out_imax) {
+    if (!ctx) return KRT_E_INVAL;
+    const std::string m = check_camera(cam);
+    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
+    if (!d_stokes || !out_flux_jy || !out_imax) return fail(ctx, KRT_E_INVAL, "NULL argument");
+    if (!ctx->units_set) return fail(ctx, KRT_E_STATE, "units not set");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    const size_t np = (size_t)cam->nx * cam->ny;
+    const double L = kG * ctx->units.M_bh_g / (kC * kC);
+    const double D = ctx->units.dist_cm;
+    const double dOm = (cam->fov_x * L / (cam->nx * D)) * (cam->fov_y * L / (cam->ny * D));
+    int nb = (int)((np + 255) / 256);
+    if (nb > kRedBlocks) nb = kRedBlocks;
+    hipLaunchKernelGGL(reduce_partial, dim3(nb), dim3(256), 0, ctx->stream, d_stokes, np, ctx->red_partial);
+    KRT_HIP(ctx, hipGetLastError());
+    double* out = ctx->red_partial + (size_t)(kRedBlocks - 1) * 9;  // last slot is free when nb < kRedBlocks
+    double* dev_out = nullptr;
+    if (nb == kRedBlocks) {
+        KRT_HIP(ctx, hipMallocAsync(reinterpret_cast<void**>(&dev_out), 8 * sizeof(double), ctx->stream));
+        out = dev_out;
+    }
+    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(1), 0, ctx->stream, ctx->red_partial, nb, 1e23 * dOm, out);
+    KRT_HIP(ctx, hipGetLastError());
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, out, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (dev_out) KRT_HIP(ctx, hipFreeAsync(dev_out, ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 4; ++k) out_flux_jy[k] = ctx->host_buf[k];
+    *out_imax = ctx->host_buf[4];
+    return KRT_OK;
+}
+
+const char* krt_last_error(const krt_ctx* ctx) {
+    if (!ctx) return "NULL context";
+    return ctx->err.c_str();
+}
+
+krt_status krt_plasma_eval(krt_ctx* ctx, int64_t n, double a, int32_t mass_factor, const double* d_X,
+                           double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_X || !d_out))) return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (!(std::fabs(a) < 1.0) || (mass_factor != 0 && mass_factor != 1))
+        return fail(ctx, KRT_E_INVAL, "bad spin or mass factor");
+    if (ctx->model < 0) return fail(ctx, KRT_E_STATE, "no plasma model set");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    krt_camera cam{};
+    cam.a = a;
+    cam.mass_factor = mass_factor;
+    TraceArgs A = base_args(ctx, &cam);
+    A.adaf.risco = isco(a);
+    hipLaunchKernelGGL(hook_plasma, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, ctx->stream, A, n, a,
+                       (double)mass_factor, d_X, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+krt_status krt_coeffs(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(hook_coeffs, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, ctx->stream, ctx->btab, n,
+                       d_in, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+krt_status krt_bessel_ratios(krt_ctx* ctx, int64_t n, const double* d_x, double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_x || !d_out))) return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(hook_bessel, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, ctx->stream, ctx->btab, n,
+                       d_x, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S, double w,
+                            double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_coef || !d_S || !d_out)) || !std::isfinite(w) || w < 0.0)
+        return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(hook_mueller, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, ctx->stream, n, d_coef,
+                       d_S, w, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,707 @@
+// Device math of the polarized Kerr ray tracer (gfx950, FP64).
+//
+// Everything here follows the method of Sec. 2.1 of Moscibrodzka & Yfantis
+// (2023) with the readings stated in krt.h: Kerr-Schild geometry, classical
+// RK4 geodesics with the eps step rule, ADAF / snapshot plasma, thermal
+// synchrotron coefficients, coherency-matrix transport and the exact
+// constant-coefficient Stokes update.  The algebra is arranged for the GPU
+// (sparse metric contractions, a closed-form propagator, table-driven Bessel
+// ratios); it is mathematically identical to the plain definitions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace krt {
+
+// CODATA 2018, cgs.
+constexpr double kC = 2.99792458e10;
+constexpr double kG = 6.67430e-8;
+constexpr double kH = 6.62607015e-27;
+constexpr double kKB = 1.380649e-16;
+constexpr double kE = 4.803204712570263e-10;
+constexpr double kME = 9.1093837015e-28;
+constexpr double kMP = 1.67262192369e-24;
+constexpr double kPi = 3.14159265358979323846;
+
+#define KRT_HD __host__ __device__ __forceinline__
+
+// True for finite x (false for inf and NaN).
+KRT_HD bool is_finite(double x) { return fabs(x) <= 1.7976931348623157e308; }
+
+// ---------------------------------------------------------------------------
+// Kerr-Schild metric at (r, theta): the seven non-zero covariant components,
+// their r and theta derivatives, and the six non-zero inverse components.
+//   g_tt = f - 1, g_tr = f, g_tp = -a f s^2, g_rr = 1 + f,
+//   g_rp = -a s^2 (1 + f), g_hh = Sigma, g_pp = s^2 (Sigma + a^2 s^2 (1 + f)),
+//   Sigma = r^2 + a^2 c^2, f = 2 m r / Sigma;
+//   g^tt = -(1 + f), g^tr = f, g^rr = Delta / Sigma, g^rp = a / Sigma,
+//   g^hh = 1 / Sigma, g^pp = 1 / (Sigma s^2), Delta = r^2 - 2 m r + a^2.
+// ---------------------------------------------------------------------------
+struct Metric {
+    double s, c;                                  // sin, cos theta
+    double Sig;
+    double tt, tr, tp, rr, rp, hh, pp;            // g_{mu nu}
+    double Itt, Itr, Irr, Irp, Ihh, Ipp;          // g^{mu nu}
+};
+
+struct MetricD {
+    double tt, tr, tp, rr, rp, hh, pp;
+};
+
+KRT_HD void metric_eval(double a, double m, double r, double th, Metric& g) {
+    double s, c;
+    sincos(th, &s, &c);
+    const double s2 = s * s;
+    const double Sig = r * r + a * a * c * c;
+    const double iS = 1.0 / Sig;
+    const double f = 2.0 * m * r * iS;
+    g.s = s;
+    g.c = c;
+    g.Sig = Sig;
+    g.tt = f - 1.0;
+    g.tr = f;
+    g.tp = -a * f * s2;
+    g.rr = 1.0 + f;
+    g.rp = -a * s2 * (1.0 + f);
+    g.hh = Sig;
+    g.pp = s2 * (Sig + a * a * s2 * (1.0 + f));
+    g.Itt = -(1.0 + f);
+    g.Itr = f;
+    g.Irr = (r * r - 2.0 * m * r + a * a) * iS;
+    g.Irp = a * iS;
+    g.Ihh = iS;
+    g.Ipp = iS / s2;
+}
+
+// Metric plus its r- and theta-derivatives.
+KRT_HD void metric_eval_d(double a, double m, double r, double th, Metric& g, MetricD& dr,
+                          MetricD& dh) {
+    metric_eval(a, m, r, th, g);
+    const double s = g.s, c = g.c, s2 = s * s, sc = s * c;
+    const double Sig = g.Sig, iS = 1.0 / Sig;
+    const double f = g.tr;
+    const double Sig_h = -2.0 * a * a * sc;
+    const double f_r = 2.0 * m * (a * a * c * c - r * r) * iS * iS;
+    const double f_h = -f * Sig_h * iS;
+    const double s2_h = 2.0 * sc;
+    const double opf = 1.0 + f;
+    dr.tt = f_r;
+    dr.tr = f_r;
+    dr.tp = -a * s2 * f_r;
+    dr.rr = f_r;
+    dr.rp = -a * s2 * f_r;
+    dr.hh = 2.0 * r;
+    dr.pp = s2 * (2.0 * r + a * a * s2 * f_r);
+    dh.tt = f_h;
+    dh.tr = f_h;
+    dh.tp = -a * (f_h * s2 + f * s2_h);
+    dh.rr = f_h;
+    dh.rp = -a * (s2_h * opf + s2 * f_h);
+    dh.hh = Sig_h;
+    dh.pp = s2_h * (Sig + a * a * s2 * opf) + s2 * (Sig_h + a * a * (s2_h * opf + s2 * f_h));
+}
+
+// Lower a vector: v_mu = g_{mu nu} v^nu.
+KRT_HD void lower(const Metric& g, const double v[4], double o[4]) {
+    o[0] = g.tt * v[0] + g.tr * v[1] + g.tp * v[3];
+    o[1] = g.tr * v[0] + g.rr * v[1] + g.rp * v[3];
+    o[2] = g.hh * v[2];
+    o[3] = g.tp * v[0] + g.rp * v[1] + g.pp * v[3];
+}
+
+// Raise a covector: v^mu = g^{mu nu} v_nu.
+KRT_HD void raise(const Metric& g, const double v[4], double o[4]) {
+    o[0] = g.Itt * v[0] + g.Itr * v[1];
+    o[1] = g.Itr * v[0] + g.Irr * v[1] + g.Irp * v[3];
+    o[2] = g.Ihh * v[2];
+    o[3] = g.Irp * v[1] + g.Ipp * v[3];
+}
+
+KRT_HD double dot(const Metric& g, const double x[4], const double y[4]) {
+    double yl[4];
+    lower(g, y, yl);
+    return x[0] * yl[0] + x[1] * yl[1] + x[2] * yl[2] + x[3] * yl[3];
+}
+
+// D . K for a derivative D of the metric (a covector).
+KRT_HD void dmetric_times(const MetricD& d, const double K[4], double o[4]) {
+    o[0] = d.tt * K[0] + d.tr * K[1] + d.tp * K[3];
+    o[1] = d.tr * K[0] + d.rr * K[1] + d.rp * K[3];
+    o[2] = d.hh * K[2];
+    o[3] = d.tp * K[0] + d.rp * K[1] + d.pp * K[3];
+}
+
+// Geodesic acceleration dK^mu/dlam = -Gamma^mu_ab K^a K^b, written as
+// -g^{mu nu} [K^r (D_r K)_nu + K^h (D_h K)_nu - 1/2 delta_nu^{r,h} K.D K]
+// (only r and theta derivatives are non-zero).
+KRT_HD void geodesic_acc(double a, double m, double r, double th, const double K[4],
+                         double acc[4]) {
+    Metric g;
+    MetricD dr, dh;
+    metric_eval_d(a, m, r, th, g, dr, dh);
+    double vr[4], vh[4];
+    dmetric_times(dr, K, vr);
+    dmetric_times(dh, K, vh);
+    const double Qr = K[0] * vr[0] + K[1] * vr[1] + K[2] * vr[2] + K[3] * vr[3];
+    const double Qh = K[0] * vh[0] + K[1] * vh[1] + K[2] * vh[2] + K[3] * vh[3];
+    double w[4];
+    for (int k = 0; k < 4; ++k) w[k] = K[1] * vr[k] + K[2] * vh[k];
+    w[1] -= 0.5 * Qr;
+    w[2] -= 0.5 * Qh;
+    double up[4];
+    raise(g, w, up);
+    for (int k = 0; k < 4; ++k) acc[k] = -up[k];
+}
+
+// Connection along the ray A^mu_b = Gamma^mu_ab K^a =
+// 1/2 g^{mu nu} [M_{nu b} + delta_b^r (D_r K)_nu + delta_b^h (D_h K)_nu
+//               - delta_nu^r (D_r K)_b - delta_nu^h (D_h K)_b],
+// M = K^r D_r g + K^h D_h g.  A is returned row-major, A[mu][b].
+KRT_HD void connection(const Metric& g, const MetricD& dr, const MetricD& dh, const double K[4],
+                       double A[16]) {
+    double vr[4], vh[4];
+    dmetric_times(dr, K, vr);
+    dmetric_times(dh, K, vh);
+    const double kr = K[1], kh = K[2];
+    double T[16];
+    // symmetric part M
+    const double Mtt = kr * dr.tt + kh * dh.tt, Mtr = kr * dr.tr + kh * dh.tr;
+    const double Mtp = kr * dr.tp + kh * dh.tp, Mrr = kr * dr.rr + kh * dh.rr;
+    const double Mrp = kr * dr.rp + kh * dh.rp, Mhh = kr * dr.hh + kh * dh.hh;
+    const double Mpp = kr * dr.pp + kh * dh.pp;
+    T[0] = Mtt;  T[1] = Mtr;  T[2] = 0.0;  T[3] = Mtp;
+    T[4] = Mtr;  T[5] = Mrr;  T[6] = 0.0;  T[7] = Mrp;
+    T[8] = 0.0;  T[9] = 0.0;  T[10] = Mhh; T[11] = 0.0;
+    T[12] = Mtp; T[13] = Mrp; T[14] = 0.0; T[15] = Mpp;
+    for (int nu = 0; nu < 4; ++nu) {
+        T[nu * 4 + 1] += vr[nu];
+        T[nu * 4 + 2] += vh[nu];
+    }
+    for (int b = 0; b < 4; ++b) {
+        T[1 * 4 + b] -= vr[b];
+        T[2 * 4 + b] -= vh[b];
+    }
+    for (int b = 0; b < 4; ++b) {
+        const double t0 = T[b], t1 = T[4 + b], t2 = T[8 + b], t3 = T[12 + b];
+        A[0 * 4 + b] = 0.5 * (g.Itt * t0 + g.Itr * t1);
+        A[1 * 4 + b] = 0.5 * (g.Itr * t0 + g.Irr * t1 + g.Irp * t3);
+        A[2 * 4 + b] = 0.5 * (g.Ihh * t2);
+        A[3 * 4 + b] = 0.5 * (g.Irp * t1 + g.Ipp * t3);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Camera: SplitMix64 jitter (Steele, Lea & Flood 2014 output function),
+// static-observer tetrad by Gram-Schmidt of (d_t, d_r, d_theta, d_phi), photon
+// launch K = e0 + n and the pixel's screen legs.
+// ---------------------------------------------------------------------------
+KRT_HD uint64_t splitmix64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+KRT_HD double pixel_jitter(uint64_t seed, uint64_t counter) {
+    const uint64_t z = splitmix64_mix(seed + counter * 0x9E3779B97F4A7C15ULL);
+    return (double)(z >> 11) * 0x1.0p-53 - 0.5;
+}
+
+struct CameraDesc {
+    double a, m, r_cam, th, ph, fov_x, fov_y, freq;
+    int nx, ny, jitter;
+    uint64_t seed;
+};
+
+KRT_HD void pixel_position(const CameraDesc& cd, int i, int j, double& alpha, double& beta) {
+    double dx = 0.0, dy = 0.0;
+    if (cd.jitter) {
+        const uint64_t k = 2ULL * ((uint64_t)j * (uint64_t)cd.nx + (uint64_t)i);
+        dx = pixel_jitter(cd.seed, k + 1ULL);
+        dy = pixel_jitter(cd.seed, k + 2ULL);
+    }
+    alpha = cd.fov_x * ((i + 0.5 + dx) / cd.nx - 0.5);
+    beta = cd.fov_y * ((j + 0.5 + dy) / cd.ny - 0.5);
+}
+
+// Static observer's orthonormal tetrad e[0..3] (contravariant) at the camera.
+KRT_HD void camera_tetrad(const CameraDesc& cd, const Metric& g, double e[4][4]) {
+    for (int k = 0; k < 4; ++k)
+        for (int mu = 0; mu < 4; ++mu) e[k][mu] = (k == mu) ? 1.0 : 0.0;
+    e[0][0] = 1.0 / sqrt(-g.tt);
+    for (int k = 1; k < 4; ++k) {
+        double v[4] = {e[k][0], e[k][1], e[k][2], e[k][3]};
+        const double p0 = dot(g, v, e[0]);
+        for (int mu = 0; mu < 4; ++mu) v[mu] += p0 * e[0][mu];
+        for (int l = 1; l < k; ++l) {
+            const double pl = dot(g, v, e[l]);
+            for (int mu = 0; mu < 4; ++mu) v[mu] -= pl * e[l][mu];
+        }
+        const double inv = 1.0 / sqrt(dot(g, v, v));
+        for (int mu = 0; mu < 4; ++mu) e[k][mu] = v[mu] * inv;
+    }
+}
+
+// Direction of travel of the arriving photon in the camera frame
+// (components on e_r, e_theta, e_phi).
+KRT_HD void arrival_direction(const CameraDesc& cd, double alpha, double beta, double n[3]) {
+    const double ra = alpha / cd.r_cam, rb = beta / cd.r_cam;
+    const double inv = 1.0 / sqrt(1.0 + ra * ra + rb * rb);
+    n[0] = inv;
+    n[1] = rb * inv;
+    n[2] = -ra * inv;
+}
+
+KRT_HD void camera_launch(const CameraDesc& cd, double alpha, double beta, double X[4],
+                          double K[4]) {
+    Metric g;
+    metric_eval(cd.a, cd.m, cd.r_cam, cd.th, g);
+    double e[4][4];
+    camera_tetrad(cd, g, e);
+    double n[3];
+    arrival_direction(cd, alpha, beta, n);
+    X[0] = 0.0;
+    X[1] = cd.r_cam;
+    X[2] = cd.th;
+    X[3] = cd.ph;
+    for (int mu = 0; mu < 4; ++mu) K[mu] = e[0][mu] + n[0] * e[1][mu] + n[1] * e[2][mu] + n[2] * e[3][mu];
+}
+
+// Screen legs of a pixel: e_x = e_phi, e_y = -e_theta made transverse to the
+// pixel's arrival direction: x' = normalised(x - (x.n) n), y' = n cross x'.
+KRT_HD void screen_legs(const CameraDesc& cd, const Metric& g, double alpha, double beta,
+                        double ex[4], double ey[4]) {
+    double e[4][4];
+    camera_tetrad(cd, g, e);
+    double n[3];
+    arrival_direction(cd, alpha, beta, n);
+    double x[3] = {-n[2] * n[0], -n[2] * n[1], 1.0 - n[2] * n[2]};
+    const double inv = 1.0 / sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    x[0] *= inv;
+    x[1] *= inv;
+    x[2] *= inv;
+    const double y[3] = {n[1] * x[2] - n[2] * x[1], n[2] * x[0] - n[0] * x[2],
+                         n[0] * x[1] - n[1] * x[0]};
+    for (int mu = 0; mu < 4; ++mu) {
+        ex[mu] = x[0] * e[1][mu] + x[1] * e[2][mu] + x[2] * e[3][mu];
+        ey[mu] = y[0] * e[1][mu] + y[1] * e[2][mu] + y[2] * e[3][mu];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plasma.
+// ---------------------------------------------------------------------------
+struct Plasma {
+    double ne, thetae, B;
+    double u[4], b[4];
+};
+
+struct AdafDesc {
+    double n0, T0, beta, h, risco;
+};
+
+// Analytic ADAF-like flow.  Returns false where no timelike flow exists.
+KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const Metric& g,
+                        Plasma& p) {
+    const double c = g.c;
+    const double sr = sqrt(r);
+    p.ne = ad.n0 / (r * sr) * exp(-c * c / (2.0 * ad.h * ad.h));
+    p.thetae = kKB * (ad.T0 / r) / (kME * kC * kC);
+    p.B = sqrt(8.0 * kPi * p.ne * kMP * kC * kC / (6.0 * r * ad.beta));
+    double Om = 0.0, norm = 1.0;
+    const bool kepler = (m != 0.0) && (r >= ad.risco);
+    if (kepler) {
+        Om = 1.0 / (r * sr + a);
+        norm = g.tt + 2.0 * g.tp * Om + g.pp * Om * Om;
+    }
+    if (!kepler || !(norm < 0.0)) {
+        Om = -g.tp / g.pp;
+        norm = g.tt + 2.0 * g.tp * Om + g.pp * Om * Om;
+    }
+    if (!(norm < 0.0)) return false;
+    const double ut = 1.0 / sqrt(-norm);
+    p.u[0] = ut;
+    p.u[1] = 0.0;
+    p.u[2] = 0.0;
+    p.u[3] = Om * ut;
+    // toroidal field b = B (d_phi + u_phi u) / sqrt(g_pp + u_phi^2)
+    const double uph = g.tp * ut + g.pp * p.u[3];
+    const double sc = p.B / sqrt(g.pp + uph * uph);
+    p.b[0] = sc * uph * p.u[0];
+    p.b[1] = 0.0;
+    p.b[2] = 0.0;
+    p.b[3] = sc * (1.0 + uph * p.u[3]);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Bessel-function ratios K0/K2 and K1/K2 of x = 1/Theta_e.
+// Table: piecewise Chebyshev series in t = ln x over [ln 1e-8, ln 700],
+// kBesPanels panels of degree kBesDeg, built at context creation from the
+// trapezoid rule on K_nu(x) e^x = int_0^inf exp(-x (cosh s - 1)) cosh(nu s) ds.
+// Outside: leading small-x forms below 1e-8, the asymptotic series above 700.
+// ---------------------------------------------------------------------------
+constexpr int kBesPanels = 64;
+constexpr int kBesDeg = 14;
+constexpr int kBesCoef = kBesDeg + 1;
+constexpr double kBesT0 = -18.420680743952367;   // ln 1e-8
+constexpr double kBesT1 = 6.551080335043404;     // ln 700
+
+// Asymptotic series of sqrt(2x/pi) e^x K_nu(x) for large x.
+KRT_HD double bessel_k_asym_series(double nu, double x) {
+    const double mu = 4.0 * nu * nu;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k <= 12; ++k) {
+        const double o = 2.0 * k - 1.0;
+        term *= (mu - o * o) / (8.0 * k * x);
+        sum += term;
+    }
+    return sum;
+}
+
+KRT_HD void bessel_ratios(const double* __restrict__ table, double x,
+                                              double& k0k2, double& k1k2) {
+    if (x > 700.0) {
+        const double s0 = bessel_k_asym_series(0.0, x), s1 = bessel_k_asym_series(1.0, x);
+        const double s2 = bessel_k_asym_series(2.0, x);
+        k0k2 = s0 / s2;
+        k1k2 = s1 / s2;
+        return;
+    }
+    if (x < 1e-8) {
+        k0k2 = 0.5 * x * x * (-log(0.5 * x) - 0.57721566490153286);
+        k1k2 = 0.5 * x;
+        return;
+    }
+    const double t = log(x);
+    const double width = (kBesT1 - kBesT0) / kBesPanels;
+    int p = (int)((t - kBesT0) / width);
+    p = p < 0 ? 0 : (p >= kBesPanels ? kBesPanels - 1 : p);
+    const double mid = kBesT0 + (p + 0.5) * width;
+    const double z = (t - mid) * (2.0 / width);
+    const double* c0 = table + (size_t)p * 2 * kBesCoef;
+    const double* c1 = c0 + kBesCoef;
+    // Clenshaw recurrences
+    double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int k = kBesDeg; k >= 1; --k) {
+        const double bt = 2.0 * z * b1 - b2 + c0[k];
+        b2 = b1;
+        b1 = bt;
+        const double dt = 2.0 * z * d1 - d2 + c1[k];
+        d2 = d1;
+        d1 = dt;
+    }
+    k0k2 = z * b1 - b2 + c0[0];
+    k1k2 = z * d1 - d2 + c1[0];
+}
+
+// ---------------------------------------------------------------------------
+// Thermal synchrotron coefficients in the fluid frame (cgs): emissivities of
+// Dexter (2016, App. A) in the basis whose second leg is along the projected
+// field, Kirchhoff absorptivities, thermal rotativities.  Returns
+// (j_I, j_Q, j_V, a_I, a_Q, a_V, r_Q, r_V) and the source function
+// B_nu / nu^3 (Kirchhoff: j = alpha B_nu).
+// ---------------------------------------------------------------------------
+KRT_HD void thermal_coefficients(const double* __restrict__ btab, double ne,
+                                                     double thetae, double B, double nu,
+                                                     double cth, double out[8]) {
+    for (int k = 0; k < 8; ++k) out[k] = 0.0;
+    if (!(ne > 0.0) || !(thetae > 0.0) || !(B > 0.0) || !(nu > 0.0)) return;
+    const double e2 = kE * kE;
+    cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
+    const double sth = sqrt(1.0 - cth * cth);
+    const double nuB = kE * B / (2.0 * kPi * kME * kC);
+    double k0k2, k1k2;
+    bessel_ratios(btab, 1.0 / thetae, k0k2, k1k2);
+    const double inu = 1.0 / nu;
+    out[7] = 2.0 * ne * e2 * nuB * cth / (kME * kC) * inu * inu * k0k2;
+    if (sth < 1e-10) return;
+
+    const double nuc = 1.5 * nuB * sth * thetae * thetae;
+    const double x = nu / nuc;
+    const double x13 = cbrt(x);
+    const double xm13 = 1.0 / x13;
+    const double xm23 = xm13 * xm13;
+    const double ex = exp(-1.8899 * x13);
+    const double II = 2.5651 * (1.0 + 1.92 * xm13 + 0.9977 * xm23) * ex;
+    const double IQ = 2.5651 * (1.0 + 0.93193 * xm13 + 0.499873 * xm23) * ex;
+    const double IV = (1.81348 / x + 3.42319 * xm23 + 0.0292545 / sqrt(x) + 2.03773 * xm13) * ex;
+    const double pre = ne * e2 * nu / (2.0 * 1.7320508075688772 * kC * thetae * thetae);
+    double jI = pre * II;
+    double jQ = pre * IQ;
+    double jV = 2.0 * ne * e2 * nu * (cth / sth) / (3.0 * 1.7320508075688772 * kC * thetae * thetae * thetae) * IV;
+    const double jP = hypot(jQ, jV);
+    if (jP > jI) {
+        const double sc = jI / jP;
+        jQ *= sc;
+        jV *= sc;
+    }
+    const double Te = thetae * kME * kC * kC / kKB;
+    const double Bnu = 2.0 * kH * nu * nu * nu / (kC * kC) / expm1(kH * nu / (kKB * Te));
+    double aI = 0.0, aQ = 0.0, aV = 0.0;
+    if (jI > 0.0 && Bnu > 0.0) {
+        aI = jI / Bnu;
+        aQ = jQ / Bnu;
+        aV = jV / Bnu;
+    }
+    out[0] = jI;
+    out[1] = jQ;
+    out[2] = jV;
+    out[3] = aI;
+    out[4] = aQ;
+    out[5] = aV;
+    out[6] = ne * e2 * nuB * nuB * sth * sth / (kME * kC) * inu * inu * inu * (k1k2 + 6.0 * thetae);
+}
+
+// Invariant source function B_nu(T_e) / nu^3 = (2 h / c^2) / expm1(h nu / k T_e).
+KRT_HD double source_function(double thetae, double nu) {
+    if (!(thetae > 0.0)) return 0.0;
+    const double Te = thetae * kME * kC * kC / kKB;
+    return 2.0 * kH / (kC * kC) / expm1(kH * nu / (kKB * Te));
+}
+
+// ---------------------------------------------------------------------------
+// Exact constant-coefficient update of dS/dl = J - K S over w for thermal
+// coefficients (J = S_eq (A_I, A_Q, 0, A_V), Kirchhoff).  K = A_I 1 + K' with
+// K' a Lorentz-algebra generator (boost part (A_Q, 0, A_V), rotation part
+// (R_Q, 0, R_V)).  With G = -K' w, whose eigenvalues are +-x and +-i y,
+//   x^2 - y^2 = w^2 (|a|^2 - |r|^2),  x y = w^2 |a.r|,
+// exp(-K w) = e^-tau (c0 + c1 G + c2 G^2 + c3 G^3), tau = A_I w,
+//   c0 = (y^2 cosh x + x^2 cos y)/(x^2+y^2), c1 = (y^2 sinh x/x + x^2 sin y/y)/(x^2+y^2),
+//   c2 = (cosh x - cos y)/(x^2+y^2),           c3 = (sinh x/x - sin y/y)/(x^2+y^2)
+// (series forms for small x^2 + y^2).  The update is written as
+//   S' = d0 S + (1 - d0) S_eq e0 + G (d1 D + G (d2 D + G d3 D)), D = S - S_eq e0,
+// d_k = e^-tau c_k, with 1 - d0 = -expm1(-tau) + e^-tau (1 - c0) free of
+// cancellation.
+// ---------------------------------------------------------------------------
+// G v with G = -w K'; K' rows (0, AQ, 0, AV), (AQ, 0, RV, 0), (0, -RV, 0, RQ), (AV, 0, -RQ, 0).
+KRT_HD void gen_apply(double AQ, double AV, double RQ, double RV, double w, const double v[4],
+                      double o[4]) {
+    o[0] = -w * (AQ * v[1] + AV * v[3]);
+    o[1] = -w * (AQ * v[0] + RV * v[2]);
+    o[2] = -w * (-RV * v[1] + RQ * v[3]);
+    o[3] = -w * (AV * v[0] - RQ * v[2]);
+}
+
+KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double RQ, double RV,
+                            double w, double S[4]) {
+    const double tau = AI * w;
+    // invariants of K' (w-scaled)
+    const double a2 = (AQ * AQ + AV * AV) * w * w;
+    const double r2 = (RQ * RQ + RV * RV) * w * w;
+    const double ar = (AQ * RQ + AV * RV) * w * w;
+    const double q = 0.5 * (a2 - r2);
+    const double rad = sqrt(q * q + ar * ar);
+    double X, Y;  // x^2 and y^2
+    if (q >= 0.0) {
+        X = rad + q;
+        Y = (X > 0.0) ? ar * ar / X : 0.0;
+    } else {
+        Y = rad - q;
+        X = (Y > 0.0) ? ar * ar / Y : 0.0;
+    }
+    const double x = sqrt(X), y = sqrt(Y);
+    const double et = exp(-tau);
+    double d0, omd0, d1, d2, d3;
+    const double XY = X + Y;
+    if (XY < 0.1) {
+        // series in X and Z = -Y: c2 = sum_k h_k/(2k)!, c3 = sum_k h_k/(2k+1)!,
+        // c0 = 1 - X Z sum_{k>=2} h_{k-1}/(2k)!, c1 = 1 - X Z sum_{k>=2} h_{k-1}/(2k+1)!,
+        // h_k = sum_{j<k} X^j Z^(k-1-j) (h_1 = 1, h_{k+1} = X h_k + Z^k).
+        const double Z = -Y;
+        double h = 1.0, zk = 1.0;
+        double fe = 2.0, fo = 6.0;  // (2k)!, (2k+1)! at k = 1
+        double c2 = 0.0, c3 = 0.0, s0 = 0.0, s1 = 0.0;
+        for (int k = 1; k <= 9; ++k) {
+            c2 += h / fe;
+            c3 += h / fo;
+            // terms of c0, c1 use h_{k} with factorials of k+1
+            const double fe1 = fe * (2 * k + 1) * (2 * k + 2);
+            const double fo1 = fo * (2 * k + 2) * (2 * k + 3);
+            s0 += h / fe1;
+            s1 += h / fo1;
+            zk *= Z;
+            h = X * h + zk;
+            fe = fe1;
+            fo = fo1;
+        }
+        const double XZ = X * Z;
+        d0 = et * (1.0 - XZ * s0);
+        omd0 = -expm1(-tau) + et * XZ * s0;
+        d1 = et * (1.0 - XZ * s1);
+        d2 = et * c2;
+        d3 = et * c3;
+    } else {
+        const double ep = exp(x - tau), em = exp(-x - tau);
+        const double ch = 0.5 * (ep + em);                  // e^-tau cosh x
+        const double shx = (x > 1e-8) ? 0.5 * (ep - em) / x : et;   // e^-tau sinh x / x
+        double sy, cy;
+        sincos(y, &sy, &cy);
+        const double syy = (y > 1e-8) ? sy / y : 1.0;
+        const double iXY = 1.0 / XY;
+        d0 = (Y * ch + X * et * cy) * iXY;
+        d1 = (Y * shx + X * et * syy) * iXY;
+        d2 = (ch - et * cy) * iXY;
+        d3 = (shx - et * syy) * iXY;
+        // e^-tau (1 - c0) = (2 X e^-tau sin^2(y/2) - 2 Y (e^-tau/2 sinh(x/2))^2) / (X + Y)
+        const double qh = 0.5 * (exp(0.5 * (x - tau)) - exp(-0.5 * (x + tau)));
+        const double snh = sin(0.5 * y);
+        omd0 = -expm1(-tau) + 2.0 * (X * et * snh * snh - Y * qh * qh) * iXY;
+    }
+    double D[4] = {S[0] - Seq, S[1], S[2], S[3]};
+    double T[4], U[4];
+    for (int k = 0; k < 4; ++k) T[k] = d3 * D[k];
+    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    for (int k = 0; k < 4; ++k) T[k] = d2 * D[k] + U[k];
+    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    for (int k = 0; k < 4; ++k) T[k] = d1 * D[k] + U[k];
+    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    S[0] = d0 * S[0] + omd0 * Seq + U[0];
+    S[1] = d0 * S[1] + U[1];
+    S[2] = d0 * S[2] + U[2];
+    S[3] = d0 * S[3] + U[3];
+}
+
+// ---------------------------------------------------------------------------
+// Coherency matrix N = NR + i NI (NR symmetric: 10 entries, NI antisymmetric:
+// 6 entries), packed upper triangles.
+// ---------------------------------------------------------------------------
+struct Coh {
+    double R[10];  // (00,01,02,03,11,12,13,22,23,33)
+    double I[6];   // (01,02,03,12,13,23)
+};
+
+KRT_HD constexpr int sym_idx(int i, int j) {
+    return (i <= j) ? (i * 4 - (i * (i - 1)) / 2 + (j - i)) : (j * 4 - (j * (j - 1)) / 2 + (i - j));
+}
+KRT_HD constexpr int asym_idx(int i, int j) {  // i < j
+    return (i == 0) ? (j - 1) : ((i == 1) ? (j + 1) : 5);
+}
+KRT_HD double nr(const Coh& N, int i, int j) { return N.R[sym_idx(i, j)]; }
+KRT_HD double ni(const Coh& N, int i, int j) {
+    return (i == j) ? 0.0 : ((i < j) ? N.I[asym_idx(i, j)] : -N.I[asym_idx(j, i)]);
+}
+
+// F(A, N) = -(A N + N A^T).
+KRT_HD void transport_rhs(const double A[16], const Coh& N, Coh& F) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i; j < 4; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) s += A[i * 4 + b] * nr(N, b, j) + nr(N, i, b) * A[j * 4 + b];
+            F.R[sym_idx(i, j)] = -s;
+        }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 4; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) s += A[i * 4 + b] * ni(N, b, j) + ni(N, i, b) * A[j * 4 + b];
+            F.I[asym_idx(i, j)] = -s;
+        }
+}
+
+// Stokes of N on two legs given as covectors l1, l2:
+// I = N11 + N22, Q = N11 - N22, U = 2 Re N12, V = -2 Im N12.
+KRT_HD void coh_project(const Coh& N, const double l1[4], const double l2[4], double S[4]) {
+    double n11 = 0.0, n22 = 0.0, n12 = 0.0, m12 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double y1 = 0.0, y2 = 0.0, z2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            y1 += nr(N, i, j) * l1[j];
+            y2 += nr(N, i, j) * l2[j];
+            z2 += ni(N, i, j) * l2[j];
+        }
+        n11 += l1[i] * y1;
+        n12 += l1[i] * y2;
+        n22 += l2[i] * y2;
+        m12 += l1[i] * z2;
+    }
+    S[0] = n11 + n22;
+    S[1] = n11 - n22;
+    S[2] = 2.0 * n12;
+    S[3] = -2.0 * m12;
+}
+
+// N from Stokes on two legs given as vectors e1, e2.
+KRT_HD void coh_rebuild(Coh& N, const double S[4], const double e1[4], const double e2[4]) {
+    const double n11 = 0.5 * (S[0] + S[1]), n22 = 0.5 * (S[0] - S[1]);
+    const double nre = 0.5 * S[2], nim = -0.5 * S[3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i; j < 4; ++j)
+            N.R[sym_idx(i, j)] = n11 * e1[i] * e1[j] + n22 * e2[i] * e2[j] + nre * (e1[i] * e2[j] + e2[i] * e1[j]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 4; ++j) N.I[asym_idx(i, j)] = nim * (e1[i] * e2[j] - e2[i] * e1[j]);
+}
+
+// ---------------------------------------------------------------------------
+// Fluid tetrad legs e1, e2 (contravariant and covariant): e0 = u,
+// e3 = unit vector along K + (K.u) u (the photon direction in the fluid
+// frame; (K + (K.u) u)/(-K.u) for exactly null K), e2 along the part of b
+// orthogonal to u and e3
+// (fallback d_theta, then d_r), e1 from the Levi-Civita tensor so that
+// (e0, e1, e2, e3) is right-handed: e1_nu = eps_{mu nu rho sigma} e0^mu e2^rho e3^sigma.
+// ---------------------------------------------------------------------------
+KRT_HD double det3(double a0, double a1, double a2, double b0, double b1, double b2, double c0,
+                   double c1, double c2) {
+    return a0 * (b1 * c2 - b2 * c1) - a1 * (b0 * c2 - b2 * c0) + a2 * (b0 * c1 - b1 * c0);
+}
+
+KRT_HD void fluid_legs(const Metric& g, const double u[4], const double K[4], const double b[4],
+                       double Ku, double e1[4], double l1[4], double e2[4], double l2[4]) {
+    double e3[4], l3[4], ul[4];
+    for (int k = 0; k < 4; ++k) e3[k] = K[k] + Ku * u[k];
+    lower(g, e3, l3);
+    const double i3 = 1.0 / sqrt(e3[0] * l3[0] + e3[1] * l3[1] + e3[2] * l3[2] + e3[3] * l3[3]);
+    for (int k = 0; k < 4; ++k) {
+        e3[k] *= i3;
+        l3[k] *= i3;
+    }
+    lower(g, u, ul);
+    // candidate along b
+    double v[4];
+    {
+        const double bu = b[0] * ul[0] + b[1] * ul[1] + b[2] * ul[2] + b[3] * ul[3];
+        const double b3 = b[0] * l3[0] + b[1] * l3[1] + b[2] * l3[2] + b[3] * l3[3];
+        for (int k = 0; k < 4; ++k) v[k] = b[k] + bu * u[k] - b3 * e3[k];
+    }
+    const double bb = dot(g, b, b);
+    const double bn = bb > 0.0 ? sqrt(bb) : 0.0;
+    double vv = dot(g, v, v);
+    double vn = vv > 0.0 ? sqrt(vv) : 0.0;
+    if (!(bn > 0.0) || !(vn >= 1e-10 * bn)) {
+        for (int c = 0; c < 2; ++c) {
+            const int dir = (c == 0) ? 2 : 1;
+            const double cn = sqrt(dir == 2 ? g.hh : g.rr);
+            const double pu = ul[dir], p3 = l3[dir];
+            for (int k = 0; k < 4; ++k) v[k] = ((k == dir) ? 1.0 : 0.0) + pu * u[k] - p3 * e3[k];
+            vv = dot(g, v, v);
+            vn = vv > 0.0 ? sqrt(vv) : 0.0;
+            if (vn >= 1e-10 * cn) break;
+        }
+    }
+    const double iv = 1.0 / vn;
+    for (int k = 0; k < 4; ++k) e2[k] = v[k] * iv;
+    lower(g, e2, l2);
+    // e1_nu from the Levi-Civita tensor, sqrt(-g) = Sigma sin(theta)
+    const double sg = g.Sig * g.s;
+    const double* P = u;
+    const double* Q = e2;
+    const double* R = e3;
+    l1[0] = -sg * det3(P[1], P[2], P[3], Q[1], Q[2], Q[3], R[1], R[2], R[3]);
+    l1[1] = sg * det3(P[0], P[2], P[3], Q[0], Q[2], Q[3], R[0], R[2], R[3]);
+    l1[2] = -sg * det3(P[0], P[1], P[3], Q[0], Q[1], Q[3], R[0], R[1], R[3]);
+    l1[3] = sg * det3(P[0], P[1], P[2], Q[0], Q[1], Q[2], R[0], R[1], R[2]);
+    raise(g, l1, e1);
+}
+
+}  // namespace krt

@@ -1,0 +1,534 @@
+// HIP kernels of the polarized Kerr ray tracer (gfx950).
+//
+// Hot path (Sec. 2.1 of Moscibrodzka & Yfantis 2023): per pixel a backward
+// geodesic, saved, then forward polarized transfer along it.  The main kernel
+// is persistent and wave-synchronous: every 64-lane wavefront takes 8x8 pixel
+// tiles from a device queue, integrates the 64 geodesics in lockstep
+// (one RK4 step per lane per iteration) into its own slice of the path store
+// (layout [point][lane][8 doubles], so each step is one coalesced 4 KiB
+// write), then walks the stored points back toward the camera with all lanes
+// aligned on the same point index (coalesced reads).  Rays longer than the
+// slice are finished by a per-lane kernel with a full-length store.
+#pragma once
+
+#include "krt_device.hpp"
+
+namespace krt {
+
+enum : uint8_t { kEscaped = 0, kCaptured = 1, kStepCap = 2, kNonFinite = 3, kAxis = 4,
+                 kRunning = 254, kOverflow = 255 };
+
+enum : int { kModelAdaf = 0, kModelSnapshot = 1 };
+
+struct TraceArgs {
+    CameraDesc cam;
+    double eps, r_stop, L_cm;
+    int max_steps;
+    int model;
+    AdafDesc adaf;
+    const double* btab;
+    // path store of the wave-synchronous kernel
+    double* pool;
+    int cap;            // stored points per lane slice
+    int tiles_x, nbatch;
+    unsigned* queue;    // [0]: next 8x8 tile
+    // long rays
+    double* long_pool;
+    int long_slots;
+    int32_t* overflow_list;
+    unsigned* overflow_count;
+    // outputs
+    double* stokes;     // [4][ny][nx]
+    uint8_t* status;    // [ny][nx] or null
+    int32_t* nsteps;    // [ny][nx] or null
+    double* end_state;  // geodesic-only mode: [ny][nx][8]
+    unsigned long long* counters;  // steps, status[5], max steps, long rays
+};
+
+// ---------------------------------------------------------------------------
+// Geodesic: state y = (r, theta, phi, K^t, K^r, K^theta, K^phi).
+// ---------------------------------------------------------------------------
+KRT_HD void geo_rhs(double a, double m, const double y[7], double d[7]) {
+    d[0] = y[4];
+    d[1] = y[5];
+    d[2] = y[6];
+    const double K[4] = {y[3], y[4], y[5], y[6]};
+    double acc[4];
+    geodesic_acc(a, m, y[0], y[1], K, acc);
+    d[3] = acc[0];
+    d[4] = acc[1];
+    d[5] = acc[2];
+    d[6] = acc[3];
+}
+
+// One classical RK4 step with |dlam| = eps / (|K^r|/r + |K^theta| + |K^phi|),
+// dlam < 0.  Returns dlam.
+KRT_HD double rk4_step(double a, double m, double eps, double y[7]) {
+    const double h = -eps / (fabs(y[4]) / y[0] + fabs(y[5]) + fabs(y[6]));
+    double k1[7], k2[7], k3[7], k4[7], yt[7];
+    geo_rhs(a, m, y, k1);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) yt[i] = y[i] + 0.5 * h * k1[i];
+    geo_rhs(a, m, yt, k2);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) yt[i] = y[i] + 0.5 * h * k2[i];
+    geo_rhs(a, m, yt, k3);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) yt[i] = y[i] + h * k3[i];
+    geo_rhs(a, m, yt, k4);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) y[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    return h;
+}
+
+// Stop rule after step n, in order: non-finite, axis, capture, escape, cap.
+KRT_HD uint8_t stop_test(const TraceArgs& A, const double y[7], double h,
+                                             int n) {
+    bool finite = is_finite(h);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) finite = finite && is_finite(y[i]);
+    if (!finite) return kNonFinite;
+    if (sin(y[1]) < 1e-12) return kAxis;
+    if (y[0] < A.r_stop) return kCaptured;
+    if (y[0] > A.cam.r_cam && y[4] * h > 0.0) return kEscaped;
+    if (n >= A.max_steps) return kStepCap;
+    return kRunning;
+}
+
+KRT_HD void store_point(double* p, const double y[7], double h) {
+    double2* q = reinterpret_cast<double2*>(p);
+    q[0] = make_double2(y[0], y[1]);
+    q[1] = make_double2(y[2], y[3]);
+    q[2] = make_double2(y[4], y[5]);
+    q[3] = make_double2(y[6], h);
+}
+
+KRT_HD void load_point(const double* p, double v[8]) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 a = q[0], b = q[1], c = q[2], d = q[3];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y;
+}
+
+// ---------------------------------------------------------------------------
+// Transfer state between stored points (Heun transport split in two halves):
+// after point n, H = N + D_n/2 F(A_n, N) and Ns = N + D_n F(A_n, N); at point
+// n-1, N = H + D_n/2 F(A_{n-1}, Ns).
+// ---------------------------------------------------------------------------
+struct XferState {
+    Coh H, Ns;
+    double Dnext;
+};
+
+KRT_HD bool plasma_at(const TraceArgs& A, double r, double th, double ph,
+                                          const Metric& g, Plasma& p) {
+    return adaf_plasma(A.adaf, A.cam.a, A.cam.m, r, g, p);
+}
+
+// Processes stored point n (first: the far end of the path).  On return N
+// holds the coherency matrix at the point after its radiative update.
+KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
+                                               bool first, XferState& st, Coh& N) {
+    const double r = pt[0], th = pt[1], ph = pt[2];
+    const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
+    const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
+    Metric g;
+    MetricD dr, dh;
+    metric_eval_d(A.cam.a, A.cam.m, r, th, g, dr, dh);
+    double Ac[16];
+    connection(g, dr, dh, K, Ac);
+    double Dnext = 0.0;
+    if (first) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+    } else {
+        Dnext = st.Dnext;
+        Coh F;
+        transport_rhs(Ac, st.Ns, F);
+        const double hh = 0.5 * Dnext;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) N.R[k] = st.H.R[k] + hh * F.R[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) N.I[k] = st.H.I[k] + hh * F.I[k];
+    }
+
+    // radiative update over w_n = (D_n + D_{n+1}) / 2
+    Plasma p;
+    if (plasma_at(A, r, th, ph, g, p)) {
+        double Kl[4];
+        lower(g, K, Kl);
+        const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
+        const double nu = A.cam.freq * (-Ku);
+        const double bb = dot(g, p.b, p.b);
+        const double bn = bb > 0.0 ? sqrt(bb) : 0.0;
+        const double cth =
+            bn > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (bn * (-Ku))
+                     : 0.0;
+        double c[8];
+        thermal_coefficients(A.btab, p.ne, p.thetae, p.B, nu, cth, c);
+        const double fac = A.L_cm / A.cam.freq * nu;
+        const double seq = (c[3] > 0.0) ? source_function(p.thetae, nu) : 0.0;
+        double e1[4], l1[4], e2[4], l2[4];
+        fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+        double S[4];
+        coh_project(N, l1, l2, S);
+        mueller_thermal(seq, fac * c[3], fac * c[4], fac * c[5], fac * c[6], fac * c[7],
+                        0.5 * (Dn + Dnext), S);
+        coh_rebuild(N, S, e1, e2);
+    }
+
+    if (n > 0) {
+        Coh F;
+        transport_rhs(Ac, N, F);
+        const double hh = 0.5 * Dn;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            st.H.R[k] = N.R[k] + hh * F.R[k];
+            st.Ns.R[k] = N.R[k] + Dn * F.R[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            st.H.I[k] = N.I[k] + hh * F.I[k];
+            st.Ns.I[k] = N.I[k] + Dn * F.I[k];
+        }
+        st.Dnext = Dn;
+    }
+}
+
+// Camera output: project N on the pixel's screen legs, times nu_obs^3.
+KRT_HD void camera_output(const TraceArgs& A, double alpha, double beta,
+                                              const Coh& N, double S[4]) {
+    Metric g;
+    metric_eval(A.cam.a, A.cam.m, A.cam.r_cam, A.cam.th, g);
+    double ex[4], ey[4], lx[4], ly[4];
+    screen_legs(A.cam, g, alpha, beta, ex, ey);
+    lower(g, ex, lx);
+    lower(g, ey, ly);
+    coh_project(N, lx, ly, S);
+    const double nu3 = A.cam.freq * A.cam.freq * A.cam.freq;
+    for (int k = 0; k < 4; ++k) S[k] *= nu3;
+}
+
+__device__ __forceinline__ void write_pixel(const TraceArgs& A, int pix, double S[4], uint8_t st,
+                                            int nst) {
+    const bool ok = is_finite(S[0]) && is_finite(S[1]) && is_finite(S[2]) && is_finite(S[3]);
+    if (!ok) {
+        S[0] = S[1] = S[2] = S[3] = 0.0;
+        st = kNonFinite;
+    }
+    const size_t np = (size_t)A.cam.nx * A.cam.ny;
+    for (int k = 0; k < 4; ++k) A.stokes[k * np + pix] = S[k];
+    if (A.status) A.status[pix] = st;
+    if (A.nsteps) A.nsteps[pix] = nst;
+}
+
+// Wave-level accounting of finished rays (one atomic per counter per wave).
+__device__ __forceinline__ void account(const TraceArgs& A, bool valid, uint8_t st, int nst) {
+    unsigned long long steps = valid ? (unsigned long long)nst : 0ULL;
+    unsigned long long mx = steps;
+    for (int off = 32; off >= 1; off >>= 1) {
+        steps += __shfl_xor(steps, off);
+        const unsigned long long o = __shfl_xor(mx, off);
+        mx = o > mx ? o : mx;
+    }
+    unsigned long long cnt[6];
+    for (int s = 0; s < 5; ++s) cnt[s] = __popcll(__ballot(valid && st == s));
+    cnt[5] = __popcll(__ballot(valid && st == kOverflow));
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&A.counters[0], steps);
+        for (int s = 0; s < 5; ++s)
+            if (cnt[s]) atomicAdd(&A.counters[1 + s], cnt[s]);
+        atomicMax(&A.counters[6], mx);
+        if (cnt[5]) atomicAdd(&A.counters[7], cnt[5]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent wave-synchronous tracer.  kGeoOnly: geodesic phase only, writing
+// the end state (no store, no transfer).
+// ---------------------------------------------------------------------------
+template <bool kGeoOnly>
+__global__ __launch_bounds__(256) void trace_waves(TraceArgs A) {
+    const int lane = threadIdx.x & 63;
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
+    for (;;) {
+        int batch = 0;
+        if (lane == 0) batch = (int)atomicAdd(A.queue, 1u);
+        batch = __shfl(batch, 0);
+        if (batch >= A.nbatch) break;
+        const int i = (batch % A.tiles_x) * 8 + (lane & 7);
+        const int j = (batch / A.tiles_x) * 8 + (lane >> 3);
+        const bool valid = i < A.cam.nx && j < A.cam.ny;
+        const int pix = j * A.cam.nx + i;
+
+        double alpha = 0.0, beta = 0.0;
+        double y[7];
+        {
+            pixel_position(A.cam, valid ? i : 0, valid ? j : 0, alpha, beta);
+            double X[4], K[4];
+            camera_launch(A.cam, alpha, beta, X, K);
+            y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
+            y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
+        }
+        if (!kGeoOnly && valid) store_point(slot + (size_t)lane * 8, y, 0.0);
+
+        // ---- backward geodesic, one step per lane per iteration ----
+        uint8_t st = valid ? kRunning : kEscaped;
+        int n = 0;
+        double hlast = 0.0;
+        while (st == kRunning) {
+            const double h = rk4_step(A.cam.a, A.cam.m, A.eps, y);
+            ++n;
+            hlast = h;
+            if (!kGeoOnly) store_point(slot + ((size_t)n * 64 + lane) * 8, y, h);
+            st = stop_test(A, y, h, n);
+            if (!kGeoOnly && st == kRunning && n >= A.cap - 1) st = kOverflow;
+        }
+
+        if (kGeoOnly) {
+            if (valid) {
+                double* e = A.end_state + (size_t)pix * 8;
+                for (int k = 0; k < 7; ++k) e[k] = y[k];
+                e[7] = hlast;
+                if (A.status) A.status[pix] = st;
+                if (A.nsteps) A.nsteps[pix] = n;
+            }
+            account(A, valid, st, n);
+            continue;
+        }
+
+        if (valid && st == kOverflow) {
+            const unsigned k = atomicAdd(A.overflow_count, 1u);
+            A.overflow_list[k] = pix;
+        }
+        account(A, valid, st, n);
+
+        // ---- transfer: all lanes on the same point index, far end first ----
+        const bool xfer = valid && st != kOverflow;
+        // a path ending in a non-finite point is transferred over its finite points
+        const int n_end = xfer ? ((st == kNonFinite) ? n - 1 : n) : -1;
+        int nmax = n_end;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int o = __shfl_xor(nmax, off);
+            nmax = o > nmax ? o : nmax;
+        }
+        XferState xs;
+        Coh N;
+        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
+        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+        for (int m = nmax; m >= 0; --m) {
+            if (m <= n_end) {
+                double pt[8];
+                load_point(slot + ((size_t)m * 64 + lane) * 8, pt);
+                transfer_point(A, pt, m, m == n_end, xs, N);
+            }
+        }
+        if (xfer) {
+            double S[4];
+            camera_output(A, alpha, beta, N, S);
+            write_pixel(A, pix, S, st, n);
+        }
+    }
+}
+
+// Rays longer than the wave-synchronous store: one ray per lane with a
+// full-length private store ([point][8]); lanes loop over the overflow list.
+__global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
+    const unsigned total = *A.overflow_count;
+    const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned stride = gridDim.x * blockDim.x;
+    double* path = A.long_pool + (size_t)tid * (size_t)(A.max_steps + 1) * 8;
+    for (unsigned k = tid; k < total; k += stride) {
+        const int pix = A.overflow_list[k];
+        const int i = pix % A.cam.nx, j = pix / A.cam.nx;
+        double alpha, beta, y[7];
+        pixel_position(A.cam, i, j, alpha, beta);
+        {
+            double X[4], K[4];
+            camera_launch(A.cam, alpha, beta, X, K);
+            y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
+            y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
+        }
+        store_point(path, y, 0.0);
+        uint8_t st = kRunning;
+        int n = 0;
+        while (st == kRunning) {
+            const double h = rk4_step(A.cam.a, A.cam.m, A.eps, y);
+            ++n;
+            store_point(path + (size_t)n * 8, y, h);
+            st = stop_test(A, y, h, n);
+        }
+        const int n_end = (st == kNonFinite) ? n - 1 : n;
+        XferState xs;
+        Coh N;
+        for (int m = n_end; m >= 0; --m) {
+            double pt[8];
+            load_point(path + (size_t)m * 8, pt);
+            transfer_point(A, pt, m, m == n_end, xs, N);
+        }
+        double S[4];
+        camera_output(A, alpha, beta, N, S);
+        write_pixel(A, pix, S, st, n);
+        // the wave-synchronous pass counted this ray as overflow; count it now
+        atomicAdd(&A.counters[0], (unsigned long long)n);
+        atomicAdd(&A.counters[1 + st], 1ULL);
+        atomicMax(&A.counters[6], (unsigned long long)n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bessel-ratio table: values at Chebyshev nodes by the trapezoid rule, then
+// coefficients.  vals: [panel][node][2].
+// ---------------------------------------------------------------------------
+KRT_HD double scaled_bessel_k(double nu, double x) {
+    // int_0^T exp(-x (cosh s - 1)) cosh(nu s) ds, trapezoid with step h; T from
+    // x (cosh T - 1) - nu T >= 45, h = min(0.1, 0.5 / sqrt(x)).
+    double T = 1.0;
+    for (int it = 0; it < 6; ++it) T = acosh(1.0 + (45.0 + nu * T) / x);
+    const double h = fmin(0.1, 0.5 / sqrt(x));
+    const int ns = (int)ceil(T / h);
+    double sum = 0.5;  // s = 0 term (weight 1/2)
+    for (int k = 1; k <= ns; ++k) {
+        const double s = k * h;
+        sum += exp(-x * (cosh(s) - 1.0)) * cosh(nu * s);
+    }
+    return sum * h;
+}
+
+__global__ void bessel_table_nodes(double* vals) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kBesPanels * kBesCoef) return;
+    const int p = idx / kBesCoef, k = idx % kBesCoef;
+    const double width = (kBesT1 - kBesT0) / kBesPanels;
+    const double mid = kBesT0 + (p + 0.5) * width;
+    const double z = cos(kPi * (k + 0.5) / kBesCoef);
+    const double x = exp(mid + 0.5 * width * z);
+    const double k0 = scaled_bessel_k(0.0, x), k1 = scaled_bessel_k(1.0, x), k2 = scaled_bessel_k(2.0, x);
+    vals[idx * 2 + 0] = k0 / k2;
+    vals[idx * 2 + 1] = k1 / k2;
+}
+
+__global__ void bessel_table_coefs(const double* vals, double* table) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kBesPanels * 2 * kBesCoef) return;
+    const int p = idx / (2 * kBesCoef), f = (idx / kBesCoef) % 2, j = idx % kBesCoef;
+    double s = 0.0;
+    for (int k = 0; k < kBesCoef; ++k)
+        s += vals[(p * kBesCoef + k) * 2 + f] * cos(kPi * j * (k + 0.5) / kBesCoef);
+    s *= 2.0 / kBesCoef;
+    if (j == 0) s *= 0.5;
+    table[(size_t)p * 2 * kBesCoef + f * kBesCoef + j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Image reduction: per-block compensated partial sums of the four Stokes
+// planes and the maximum of I, then one block combining them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+    const double t = s + x;
+    if (fabs(s) >= fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+__global__ __launch_bounds__(256) void reduce_partial(const double* __restrict__ stokes, size_t np,
+                                                      double* partial) {
+    __shared__ double sh[256 * 9];
+    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0}, mx = -INFINITY;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < np;
+         k += (size_t)gridDim.x * blockDim.x) {
+        for (int q = 0; q < 4; ++q) neumaier_add(s[q], c[q], stokes[q * np + k]);
+        mx = fmax(mx, stokes[k]);
+    }
+    for (int q = 0; q < 4; ++q) {
+        sh[threadIdx.x * 9 + 2 * q] = s[q];
+        sh[threadIdx.x * 9 + 2 * q + 1] = c[q];
+    }
+    sh[threadIdx.x * 9 + 8] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S[4] = {0, 0, 0, 0}, Cc[4] = {0, 0, 0, 0}, M = -INFINITY;
+        for (int t = 0; t < (int)blockDim.x; ++t) {
+            for (int q = 0; q < 4; ++q) {
+                neumaier_add(S[q], Cc[q], sh[t * 9 + 2 * q]);
+                Cc[q] += sh[t * 9 + 2 * q + 1];
+            }
+            M = fmax(M, sh[t * 9 + 8]);
+        }
+        for (int q = 0; q < 4; ++q) {
+            partial[blockIdx.x * 9 + 2 * q] = S[q];
+            partial[blockIdx.x * 9 + 2 * q + 1] = Cc[q];
+        }
+        partial[blockIdx.x * 9 + 8] = M;
+    }
+}
+
+__global__ void reduce_final(const double* partial, int nblocks, double scale, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double S[4] = {0, 0, 0, 0}, Cc[4] = {0, 0, 0, 0}, M = -INFINITY;
+    for (int b = 0; b < nblocks; ++b) {
+        for (int q = 0; q < 4; ++q) {
+            neumaier_add(S[q], Cc[q], partial[b * 9 + 2 * q]);
+            Cc[q] += partial[b * 9 + 2 * q + 1];
+        }
+        M = fmax(M, partial[b * 9 + 8]);
+    }
+    for (int q = 0; q < 4; ++q) out[q] = scale * (S[q] + Cc[q]);
+    out[4] = M;
+}
+
+// ---------------------------------------------------------------------------
+// Component hooks.
+// ---------------------------------------------------------------------------
+__global__ void hook_plasma(TraceArgs A, int64_t n, double a, double m, const double* X,
+                            double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double r = X[k * 3], th = X[k * 3 + 1], ph = X[k * 3 + 2];
+    Metric g;
+    metric_eval(a, m, r, th, g);
+    Plasma p;
+    TraceArgs B = A;
+    B.cam.a = a;
+    B.cam.m = m;
+    const bool ok = plasma_at(B, r, th, ph, g, p);
+    double* o = out + k * 12;
+    o[0] = p.ne; o[1] = p.thetae; o[2] = p.B;
+    for (int q = 0; q < 4; ++q) {
+        o[3 + q] = ok ? p.u[q] : 0.0;
+        o[7 + q] = ok ? p.b[q] : 0.0;
+    }
+    o[11] = ok ? 1.0 : 0.0;
+}
+
+__global__ void hook_coeffs(const double* btab, int64_t n, const double* in, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double* v = in + k * 5;
+    double c[8];
+    thermal_coefficients(btab, v[0], v[1], v[2], v[3], v[4], c);
+    for (int q = 0; q < 8; ++q) out[k * 8 + q] = c[q];
+}
+
+__global__ void hook_bessel(const double* btab, int64_t n, const double* x, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double a, b;
+    bessel_ratios(btab, x[k], a, b);
+    out[2 * k] = a;
+    out[2 * k + 1] = b;
+}
+
+__global__ void hook_mueller(int64_t n, const double* coef, const double* S, double w, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double* c = coef + k * 6;
+    double s[4] = {S[k * 4], S[k * 4 + 1], S[k * 4 + 2], S[k * 4 + 3]};
+    mueller_thermal(c[0], c[1], c[2], c[3], c[4], c[5], w, s);
+    for (int q = 0; q < 4; ++q) out[k * 4 + q] = s[q];
+}
+
+}  // namespace krt

@@ -1,0 +1,260 @@
+"""Thin ctypes binding of libkrt.so (include/krt.h).
+
+Argument marshalling only: every step of the ray-tracing path runs in the HIP
+kernels of libkrt.so.  PyTorch provides device memory and the stream.  The
+binding fails loudly when the library is missing; there is no fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkrt.so")
+
+OK, E_INVAL, E_NOMEM, E_HIP, E_STATE, E_UNSUPPORTED = range(6)
+RAY_ESCAPED, RAY_CAPTURED, RAY_STEP_CAP, RAY_NONFINITE, RAY_AXIS = range(5)
+
+
+class KrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"krt error {code}: {msg}")
+        self.code = code
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("a", ctypes.c_double), ("incl_deg", ctypes.c_double),
+        ("phi_deg", ctypes.c_double), ("r_cam", ctypes.c_double), ("fov_x", ctypes.c_double),
+        ("fov_y", ctypes.c_double), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("freq_hz", ctypes.c_double), ("eps", ctypes.c_double), ("max_steps", ctypes.c_int32),
+        ("jitter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mass_factor", ctypes.c_int32),
+    ]
+
+
+class Units(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("M_bh_g", ctypes.c_double),
+                ("dist_cm", ctypes.c_double)]
+
+
+class Adaf(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("n0_cgs", ctypes.c_double),
+                ("T0_K", ctypes.c_double), ("beta", ctypes.c_double),
+                ("h_over_r", ctypes.c_double), ("field_geom", ctypes.c_int32)]
+
+
+class SnapshotDesc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+        ("n3", ctypes.c_int32), ("x1_start", ctypes.c_double), ("dx1", ctypes.c_double),
+        ("x2_start", ctypes.c_double), ("dx2", ctypes.c_double), ("x3_start", ctypes.c_double),
+        ("dx3", ctypes.c_double), ("hslope", ctypes.c_double), ("gamma_ad", ctypes.c_double),
+        ("M_unit_g", ctypes.c_double), ("R_high", ctypes.c_double), ("R_low", ctypes.c_double),
+        ("sigma_cut", ctypes.c_double), ("r_emit_max", ctypes.c_double), ("layout", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("rays", ctypes.c_int64),
+                ("total_steps", ctypes.c_int64), ("status_count", ctypes.c_int64 * 5),
+                ("max_steps_seen", ctypes.c_int32), ("long_rays", ctypes.c_int64),
+                ("kernel_ms", ctypes.c_double * 2)]
+
+    def as_dict(self):
+        return {"rays": self.rays, "total_steps": self.total_steps,
+                "status_count": list(self.status_count), "max_steps_seen": self.max_steps_seen,
+                "long_rays": self.long_rays, "kernel_ms": list(self.kernel_ms)}
+
+
+# Every symbol include/krt.h declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_SIGS = {
+    "krt_abi_version": (ctypes.c_int, []),
+    "krt_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)]),
+    "krt_destroy": (ctypes.c_int, [_P]),
+    "krt_set_stream": (ctypes.c_int, [_P, _P]),
+    "krt_set_units": (ctypes.c_int, [_P, ctypes.POINTER(Units)]),
+    "krt_set_model_adaf": (ctypes.c_int, [_P, ctypes.POINTER(Adaf)]),
+    "krt_set_model_snapshot": (ctypes.c_int, [_P, ctypes.POINTER(SnapshotDesc), _P, ctypes.c_int]),
+    "krt_trace": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, ctypes.POINTER(Stats)]),
+    "krt_trace_steps": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P, ctypes.POINTER(Stats)]),
+    "krt_reduce": (ctypes.c_int, [_P, _P, ctypes.POINTER(Camera), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]),
+    "krt_last_error": (ctypes.c_char_p, [_P]),
+    "krt_check_camera": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_char_p, ctypes.c_size_t]),
+    "krt_geodesic_only": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P]),
+    "krt_plasma_eval": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P]),
+    "krt_coeffs": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
+    "krt_bessel_ratios": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
+    "krt_mueller_step": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_double, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libkrt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2302_02733_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def make_camera(d):
+    c = Camera()
+    c.struct_size = ctypes.sizeof(Camera)
+    for name, _ in Camera._fields_[1:]:
+        setattr(c, name, d[name])
+    return c
+
+
+def check_camera(d):
+    """Host-only validation; returns '' when valid, else the message."""
+    c = make_camera(d)
+    buf = ctypes.create_string_buffer(256)
+    rc = lib().krt_check_camera(ctypes.byref(c), buf, 256)
+    return "" if rc == OK else buf.value.decode()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, device):
+    if t.device != device:
+        raise ValueError(f"tensor on {t.device}, context on {device}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device=0):
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = lib().krt_create(device, ctypes.byref(h))
+        if rc != OK:
+            raise KrtError(rc, "krt_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().krt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc != OK:
+            raise KrtError(rc, lib().krt_last_error(self.h).decode())
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device)
+        self._check(lib().krt_set_stream(self.h, ctypes.c_void_p(s.cuda_stream)))
+
+    def set_units(self, d):
+        u = Units(ctypes.sizeof(Units), d["M_bh_g"], d["dist_cm"])
+        self._check(lib().krt_set_units(self.h, ctypes.byref(u)))
+
+    def set_model_adaf(self, d):
+        m = Adaf(ctypes.sizeof(Adaf), d["n0_cgs"], d["T0_K"], d["beta"], d["h_over_r"],
+                 int(d.get("field_geom", 0)))
+        self._check(lib().krt_set_model_adaf(self.h, ctypes.byref(m)))
+
+    def set_model(self, d):
+        kind = int(d.get("kind", 0))
+        if kind == 0:
+            return self.set_model_adaf(d)
+        raise ValueError(f"unsupported model kind {kind}")
+
+    def trace(self, cam, stokes=None, status=None, nsteps=None, stats=True):
+        """Traces the image; returns dict(stokes [4,ny,nx] f64, status [ny,nx] u8,
+        nsteps [ny,nx] i32 or None, stats dict or None)."""
+        nx, ny = cam["nx"], cam["ny"]
+        if stokes is None:
+            stokes = torch.empty((4, ny, nx), dtype=torch.float64, device=self.device)
+        if status is None:
+            status = torch.empty((ny, nx), dtype=torch.uint8, device=self.device)
+        for t, shape, dt in ((stokes, (4, ny, nx), torch.float64), (status, (ny, nx), torch.uint8)):
+            _dev(t, self.device)
+            if tuple(t.shape) != shape or t.dtype != dt:
+                raise ValueError("bad output tensor")
+        if nsteps is not None:
+            _dev(nsteps, self.device)
+            if tuple(nsteps.shape) != (ny, nx) or nsteps.dtype != torch.int32:
+                raise ValueError("bad nsteps tensor")
+        c = make_camera(cam)
+        st = Stats()
+        st.struct_size = ctypes.sizeof(Stats)
+        self._stream()
+        self._check(lib().krt_trace_steps(self.h, ctypes.byref(c), _ptr(stokes), _ptr(status),
+                                          _ptr(nsteps), ctypes.byref(st) if stats else None))
+        return {"stokes": stokes, "status": status, "nsteps": nsteps,
+                "stats": st.as_dict() if stats else None}
+
+    def reduce(self, stokes, cam):
+        """Returns (flux_jy[4], I_max); synchronises."""
+        _dev(stokes, self.device)
+        c = make_camera(cam)
+        flux = (ctypes.c_double * 4)()
+        imax = ctypes.c_double()
+        self._stream()
+        self._check(lib().krt_reduce(self.h, _ptr(stokes), ctypes.byref(c), flux, ctypes.byref(imax)))
+        return list(flux), imax.value
+
+    def geodesic_only(self, cam):
+        nx, ny = cam["nx"], cam["ny"]
+        end = torch.empty((ny, nx, 8), dtype=torch.float64, device=self.device)
+        ns = torch.empty((ny, nx), dtype=torch.int32, device=self.device)
+        st = torch.empty((ny, nx), dtype=torch.uint8, device=self.device)
+        c = make_camera(cam)
+        self._stream()
+        self._check(lib().krt_geodesic_only(self.h, ctypes.byref(c), _ptr(end), _ptr(ns), _ptr(st)))
+        return end, ns, st
+
+    def plasma_eval(self, X, a, mass_factor=1):
+        X = _dev(X, self.device)
+        out = torch.empty((X.shape[0], 12), dtype=torch.float64, device=self.device)
+        self._stream()
+        self._check(lib().krt_plasma_eval(self.h, X.shape[0], a, mass_factor, _ptr(X), _ptr(out)))
+        return out
+
+    def coeffs(self, inp):
+        inp = _dev(inp, self.device)
+        out = torch.empty((inp.shape[0], 8), dtype=torch.float64, device=self.device)
+        self._stream()
+        self._check(lib().krt_coeffs(self.h, inp.shape[0], _ptr(inp), _ptr(out)))
+        return out
+
+    def bessel_ratios(self, x):
+        x = _dev(x, self.device)
+        out = torch.empty((x.shape[0], 2), dtype=torch.float64, device=self.device)
+        self._stream()
+        self._check(lib().krt_bessel_ratios(self.h, x.shape[0], _ptr(x), _ptr(out)))
+        return out
+
+    def mueller_step(self, coef, S, w):
+        coef, S = _dev(coef, self.device), _dev(S, self.device)
+        out = torch.empty_like(S)
+        self._stream()
+        self._check(lib().krt_mueller_step(self.h, coef.shape[0], _ptr(coef), _ptr(S), float(w), _ptr(out)))
+        return out

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: images -- total-flux relative error <= 1e-10 and 99th-percentile
+|dS|/max(I) <= 1e-8 per Stokes parameter, identical ray status and step
+counts; components -- agreement to round-off (tolerances per test).
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2302_02733_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FLUX_TOL = 1e-10
+P99_TOL = 1e-8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_02733_amd import krt
+    c = krt.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_image(ctx, w, nsteps=True):
+    ctx.set_units(w["units"])
+    ctx.set_model(w["model"])
+    cam = w["camera"]
+    ns = torch.empty((cam["ny"], cam["nx"]), dtype=torch.int32, device=ctx.device) if nsteps else None
+    out = ctx.trace(cam, nsteps=ns)
+    torch.cuda.synchronize()
+    return out
+
+
+def _compare_images(S, So, st=None, sto=None, ns=None, nso=None):
+    imax = So[0].max()
+    assert imax > 0
+    for s in range(4):
+        d = np.abs(S[s] - So[s]).ravel() / imax
+        p99 = np.percentile(d, 99)
+        assert p99 <= P99_TOL, (s, p99, d.max())
+    flux, fo = S[0].sum(), So[0].sum()
+    assert abs(flux - fo) / fo <= FLUX_TOL
+    for s in range(1, 4):
+        assert abs(S[s].sum() - So[s].sum()) / fo <= FLUX_TOL
+    if st is not None:
+        assert np.array_equal(st, sto)
+    if ns is not None:
+        assert np.mean(ns == nso) >= 0.999
+        assert np.abs(ns - nso).max() <= 2
+
+
+# ---------------- components ----------------
+
+def test_bessel_ratios(ctx):
+    x = np.concatenate([10 ** np.linspace(-10, 4, 700), [700.0, 700.0000001, 1e-8, 0.99999e-8]])
+    out = ctx.bessel_ratios(torch.tensor(x, device=ctx.device)).cpu().numpy()
+    ref = np.array([oracle.bessel_ratios(v) for v in x])
+    assert np.max(np.abs(out - ref) / np.abs(ref)) < 2e-13
+
+
+def test_thermal_coefficients(ctx):
+    rng = np.random.default_rng(4)
+    n = 4000
+    inp = np.stack([10 ** rng.uniform(1, 9, n), 10 ** rng.uniform(-2, 3, n), 10 ** rng.uniform(-2, 3.5, n),
+                    10 ** rng.uniform(9, 13, n), rng.uniform(-1, 1, n)], 1)
+    inp[:20, 4] = 1.0          # field along the ray
+    inp[20:40, 0] = 0.0        # no plasma
+    inp[40:60, 1] = 1e-9       # cold plasma (asymptotic Bessel branch)
+    out = ctx.coeffs(torch.tensor(inp, device=ctx.device)).cpu().numpy()
+    ref = np.array([oracle.thermal_coefficients(*r) for r in inp])
+    scale = np.maximum(np.abs(ref), 1e-300)
+    rel = np.where(np.abs(ref) > 0, np.abs(out - ref) / scale, np.abs(out))
+    assert rel.max() < 1e-12
+
+
+def test_mueller_step(ctx):
+    rng = np.random.default_rng(6)
+    n = 3000
+    co = np.zeros((n, 6))
+    S = rng.normal(size=(n, 4))
+    S[:, 0] = np.abs(S[:, 0]) + np.sqrt((S[:, 1:] ** 2).sum(1))
+    scale = 10 ** rng.uniform(-9, 2, n)
+    co[:, 0] = 10 ** rng.uniform(-2, 2, n)
+    co[:, 1] = scale * rng.uniform(0.5, 2, n)
+    co[:, 2] = co[:, 1] * rng.uniform(-0.7, 0.7, n)
+    co[:, 3] = co[:, 1] * rng.uniform(-0.5, 0.5, n)
+    co[:, 4] = scale * 10 ** rng.uniform(-3, 3, n) * rng.choice([-1, 1], n)
+    co[:, 5] = scale * 10 ** rng.uniform(-3, 4, n) * rng.choice([-1, 1], n)
+    co[:10, 1:] = 0.0          # empty medium
+    for w in (1.0, 0.01, 30.0):
+        out = ctx.mueller_step(torch.tensor(co, device=ctx.device), torch.tensor(S, device=ctx.device), w)
+        out = out.cpu().numpy()
+        ref = np.array([oracle.mueller_step([c[0] * c[1], c[0] * c[2], c[0] * c[3], *c[1:]], s, w)
+                        for c, s in zip(co, S)])
+        err = np.abs(out - ref).max(1) / np.maximum(np.abs(ref[:, 0]), np.abs(S[:, 0]))
+        assert err.max() < 1e-11, (w, err.max())
+
+
+def test_adaf_plasma(ctx):
+    rng = np.random.default_rng(8)
+    n = 500
+    a = 0.9375
+    X = np.stack([10 ** rng.uniform(np.log10(1.4), 3, n), rng.uniform(0.01, np.pi - 0.01, n),
+                  rng.uniform(-10, 10, n)], 1)
+    ctx.set_model(W.ADAF)
+    out = ctx.plasma_eval(torch.tensor(X, device=ctx.device), a, 1).cpu().numpy()
+    for k in range(n):
+        p = oracle.plasma(W.ADAF, a, 1.0, *X[k])
+        ref = np.concatenate([[p["ne"], p["thetae"], p["B"]], p["u"], p["b"], [1.0 if p["valid"] else 0.0]])
+        np.testing.assert_allclose(out[k], ref, rtol=1e-13, atol=1e-13 * np.abs(ref[3:11]).max())
+
+
+# ---------------- geodesics ----------------
+
+def test_geodesic_end_states(ctx):
+    cam = W.adaf_camera(32)
+    ctx.set_units(W.UNITS)
+    ctx.set_model(W.ADAF)
+    end, ns, st = ctx.geodesic_only(cam)
+    end, ns, st = end.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
+    for j in range(0, 32, 3):
+        for i in range(0, 32, 3):
+            al, be = oracle.pixel_position(cam, i, j)
+            path, sto = oracle.trace_ray(cam, al, be)
+            assert st[j, i] == sto
+            assert ns[j, i] == len(path) - 1
+            ref = np.concatenate([path[-1, :3], path[-1, 3:7], [path[-1, 7]]])
+            got = np.concatenate([end[j, i, :3], end[j, i, 3:7], [end[j, i, 7]]])
+            np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+# ---------------- images ----------------
+
+@pytest.fixture(scope="module")
+def adaf64_oracle():
+    w = W.workload("adaf64")
+    S, st, ns = oracle.render(w["camera"], w["units"], w["model"])
+    return w, S, st, ns
+
+
+def test_image_parity_adaf64(ctx, adaf64_oracle):
+    w, So, sto, nso = adaf64_oracle
+    out = _gpu_image(ctx, w)
+    S = out["stokes"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    ns = out["nsteps"].cpu().numpy()
+    _compare_images(S, So, st, sto, ns, nso)
+    stats = out["stats"]
+    assert stats["rays"] == 64 * 64
+    assert stats["total_steps"] == int(ns.sum())
+    assert sum(stats["status_count"]) == 64 * 64
+    assert stats["max_steps_seen"] == int(ns.max())
+
+
+def test_reduce_matches_oracle(ctx, adaf64_oracle):
+    w, So, sto, nso = adaf64_oracle
+    out = _gpu_image(ctx, w, nsteps=False)
+    flux, imax = ctx.reduce(out["stokes"], w["camera"])
+    fo, imo = oracle.reduce(w["camera"], w["units"], out["stokes"].cpu().numpy())
+    np.testing.assert_allclose(flux, fo, rtol=1e-14, atol=1e-14 * abs(fo[0]))
+    assert imax == imo
+    fo2, _ = oracle.reduce(w["camera"], w["units"], So)
+    assert abs(flux[0] - fo2[0]) / fo2[0] <= FLUX_TOL
+
+
+def test_ragged_image_and_long_ray_path(ctx):
+    """A 37 x 23 image (ragged 8x8 tiles), with a tiny wave store so that most
+    rays take the long-ray kernel."""
+    cam = W.adaf_camera(37, fov=30.0)
+    cam.update(ny=23, fov_y=20.0, seed=12345)
+    w = {"camera": cam, "model": W.ADAF, "units": W.UNITS}
+    So, sto, nso = oracle.render(cam, W.UNITS, W.ADAF)
+    out = _gpu_image(ctx, w)
+    _compare_images(out["stokes"].cpu().numpy(), So, out["status"].cpu().numpy(), sto,
+                    out["nsteps"].cpu().numpy(), nso)
+    os.environ["KRT_PATH_CAP"] = "700"
+    try:
+        out2 = _gpu_image(ctx, w)
+        assert out2["stats"]["long_rays"] > 0
+        _compare_images(out2["stokes"].cpu().numpy(), So, out2["status"].cpu().numpy(), sto,
+                        out2["nsteps"].cpu().numpy(), nso)
+    finally:
+        del os.environ["KRT_PATH_CAP"]
+
+
+def test_single_pixel_and_step_cap(ctx):
+    cam = W.adaf_camera(1, fov=10.0)
+    w = {"camera": cam, "model": W.ADAF, "units": W.UNITS}
+    So, sto, nso = oracle.render(cam, W.UNITS, W.ADAF)
+    out = _gpu_image(ctx, w)
+    np.testing.assert_allclose(out["stokes"].cpu().numpy(), So, rtol=1e-9, atol=1e-9 * So[0].max())
+    cam2 = W.adaf_camera(16, max_steps=10)
+    w2 = {"camera": cam2, "model": W.ADAF, "units": W.UNITS}
+    So2, sto2, nso2 = oracle.render(cam2, W.UNITS, W.ADAF)
+    out2 = _gpu_image(ctx, w2)
+    assert np.all(out2["status"].cpu().numpy() == oracle.STEP_CAP)
+    assert np.all(out2["nsteps"].cpu().numpy() == 10)
+    np.testing.assert_allclose(out2["stokes"].cpu().numpy(), So2, rtol=1e-10, atol=1e-10 * abs(So2).max())
+
+
+def test_invalid_camera_rejected_before_launch(ctx):
+    from paper_2302_02733_amd import krt
+    cam = W.adaf_camera(8, eps=0.0)
+    with pytest.raises(krt.KrtError) as e:
+        ctx.trace(cam)
+    assert e.value.code == krt.E_INVAL
+
+
+@pytest.mark.parametrize("n", [1024])
+def test_full_size_sampled_parity(ctx, n):
+    """The bench workload (ADAF, n x n) in the bench's launch configuration,
+    checked on a seeded sample of pixels the oracle computes one by one."""
+    w = W.workload(f"adaf{n}")
+    out = _gpu_image(ctx, w)
+    pix = W.pixel_sample(n, n, 96, 2024)
+    So, sto, nso = oracle.render(w["camera"], w["units"], w["model"], pixels=pix)
+    S = out["stokes"].reshape(4, -1)[:, torch.tensor(pix, device=ctx.device)].cpu().numpy()
+    st = out["status"].reshape(-1)[torch.tensor(pix, device=ctx.device)].cpu().numpy()
+    ns = out["nsteps"].reshape(-1)[torch.tensor(pix, device=ctx.device)].cpu().numpy()
+    assert np.array_equal(st, sto)
+    assert np.array_equal(ns, nso)
+    scale = np.abs(So[0]).max()
+    assert np.abs(S - So).max() / scale < 1e-8
+    # properties that hold at any size: realizability, non-negative I, status counts
+    I, Q, U, V = out["stokes"].cpu().numpy()
+    assert np.all(I >= 0)
+    assert np.all(I * I * (1 + 1e-12) >= Q * Q + U * U + V * V)
+    assert out["stats"]["rays"] == n * n == sum(out["stats"]["status_count"])
