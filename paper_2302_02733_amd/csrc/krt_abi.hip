@@ -270,7 +270,7 @@ krt_status krt_create(int device, krt_ctx** out) {
         if (e != hipSuccess) { st = hip_fail(ctx, e, "hipGetDeviceProperties"); break; }
         ctx->cu_count = prop.multiProcessorCount;
         if (hipMalloc(&ctx->work, kWorkWords * sizeof(unsigned)) != hipSuccess ||
-            hipMalloc(&ctx->red_partial, kRedBlocks * 9 * sizeof(double)) != hipSuccess ||
+            hipMalloc(&ctx->red_partial, (kRedBlocks * 9 + 16) * sizeof(double)) != hipSuccess ||
             hipMalloc(&ctx->btab, (size_t)kBesPanels * 2 * kBesCoef * sizeof(double)) != hipSuccess ||
             hipHostMalloc(&ctx->host_buf, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
             hipEventCreate(&ctx->ev[0]) != hipSuccess || hipEventCreate(&ctx->ev[1]) != hipSuccess ||
@@ -430,16 +430,10 @@ krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* ca
     if (nb > kRedBlocks) nb = kRedBlocks;
     hipLaunchKernelGGL(reduce_partial, dim3(nb), dim3(256), 0, ctx->stream, d_stokes, np, ctx->red_partial);
     KRT_HIP(ctx, hipGetLastError());
-    double* out = ctx->red_partial + (size_t)(kRedBlocks - 1) * 9;  // last slot is free when nb < kRedBlocks
-    double* dev_out = nullptr;
-    if (nb == kRedBlocks) {
-        KRT_HIP(ctx, hipMallocAsync(reinterpret_cast<void**>(&dev_out), 8 * sizeof(double), ctx->stream));
-        out = dev_out;
-    }
+    double* out = ctx->red_partial + (size_t)kRedBlocks * 9;  // 16 doubles after the partials
     hipLaunchKernelGGL(reduce_final, dim3(1), dim3(1), 0, ctx->stream, ctx->red_partial, nb, 1e23 * dOm, out);
     KRT_HIP(ctx, hipGetLastError());
     KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, out, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    if (dev_out) KRT_HIP(ctx, hipFreeAsync(dev_out, ctx->stream));
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k < 4; ++k) out_flux_jy[k] = ctx->host_buf[k];
     *out_imax = ctx->host_buf[4];
