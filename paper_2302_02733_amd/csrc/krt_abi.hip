@@ -22,6 +22,8 @@ struct krt_ctx {
     krt_units units{};
     int model = -1;
     krt_adaf adaf{};
+    krt_snapshot_desc snap{};
+    const double* snap_prims = nullptr;
     double* btab = nullptr;
     // wave-synchronous path store
     double* pool = nullptr;
@@ -129,7 +131,29 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     A.r_stop = cam->mass_factor == 0 ? 1e-6 : 1.05 * horizon(cam->a, 1.0);
     A.L_cm = ctx->units_set ? kG * ctx->units.M_bh_g / (kC * kC) : 0.0;
     A.max_steps = cam->max_steps;
-    A.model = kModelAdaf;
+    A.model = ctx->model < 0 ? kModelAdaf : ctx->model;
+    if (ctx->model == kModelSnapshot) {
+        const krt_snapshot_desc& d = ctx->snap;
+        const double L = A.L_cm;
+        A.snap.prims = ctx->snap_prims;
+        A.snap.n1 = d.n1;
+        A.snap.n2 = d.n2;
+        A.snap.n3 = d.n3;
+        A.snap.x1s = d.x1_start;
+        A.snap.dx1 = d.dx1;
+        A.snap.x2s = d.x2_start;
+        A.snap.dx2 = d.dx2;
+        A.snap.x3s = d.x3_start;
+        A.snap.dx3 = d.dx3;
+        A.snap.h = d.hslope;
+        A.snap.gam = d.gamma_ad;
+        A.snap.rho_unit = L > 0.0 ? d.M_unit_g / (L * L * L) : 0.0;
+        A.snap.B_unit = kC * std::sqrt(4.0 * kPi * A.snap.rho_unit);
+        A.snap.Rhigh = d.R_high;
+        A.snap.Rlow = d.R_low;
+        A.snap.sigma_cut = d.sigma_cut;
+        A.snap.rmax = d.r_emit_max;
+    }
     A.adaf.n0 = ctx->adaf.n0_cgs;
     A.adaf.T0 = ctx->adaf.T0_K;
     A.adaf.beta = ctx->adaf.beta;
@@ -353,10 +377,23 @@ krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* p) {
 krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, const void* d_prims,
                                   int dtype) {
     if (!ctx) return KRT_E_INVAL;
-    (void)desc;
-    (void)d_prims;
-    (void)dtype;
-    return fail(ctx, KRT_E_UNSUPPORTED, "snapshot model not available in this build");
+    if (!desc || desc->struct_size != sizeof(krt_snapshot_desc)) return fail(ctx, KRT_E_INVAL, "bad snapshot struct");
+    if (!d_prims) return fail(ctx, KRT_E_INVAL, "d_prims is NULL");
+    if (dtype != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only FP64 primitives (dtype 0) are supported");
+    if (desc->layout != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only layout 0 is supported");
+    const krt_snapshot_desc& d = *desc;
+    if (d.n1 < 2 || d.n2 < 2 || d.n3 < 1) return fail(ctx, KRT_E_INVAL, "grid needs n1, n2 >= 2 and n3 >= 1");
+    if ((int64_t)d.n1 * d.n2 * d.n3 > ((int64_t)1 << 31) / 8) return fail(ctx, KRT_E_INVAL, "grid too large");
+    if (!finite_all({d.x1_start, d.dx1, d.x2_start, d.dx2, d.x3_start, d.dx3, d.hslope, d.gamma_ad, d.M_unit_g,
+                     d.R_high, d.R_low, d.sigma_cut, d.r_emit_max}))
+        return fail(ctx, KRT_E_INVAL, "snapshot description has a non-finite field");
+    if (!(d.dx1 > 0.0 && d.dx2 > 0.0 && d.dx3 > 0.0)) return fail(ctx, KRT_E_INVAL, "cell sizes must be > 0");
+    if (!(d.M_unit_g > 0.0) || !(d.gamma_ad > 1.0)) return fail(ctx, KRT_E_INVAL, "need M_unit > 0, gamma_ad > 1");
+    if (!(d.hslope > 0.0 && d.hslope <= 1.0)) return fail(ctx, KRT_E_INVAL, "hslope must be in (0, 1]");
+    ctx->snap = d;
+    ctx->snap_prims = static_cast<const double*>(d_prims);
+    ctx->model = kModelSnapshot;
+    return KRT_OK;
 }
 
 krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
@@ -452,6 +489,7 @@ krt_status krt_plasma_eval(krt_ctx* ctx, int64_t n, double a, int32_t mass_facto
     if (!(std::fabs(a) < 1.0) || (mass_factor != 0 && mass_factor != 1))
         return fail(ctx, KRT_E_INVAL, "bad spin or mass factor");
     if (ctx->model < 0) return fail(ctx, KRT_E_STATE, "no plasma model set");
+    if (ctx->model == kModelSnapshot && !ctx->units_set) return fail(ctx, KRT_E_STATE, "units not set");
     if (n == 0) return KRT_OK;
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     krt_camera cam{};

@@ -334,6 +334,117 @@ KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const 
     return true;
 }
 
+// Gridded snapshot on a modified Kerr-Schild grid: x1 = ln r,
+// theta = pi x2 + (1 - h)/2 sin(2 pi x2), x3 = phi; cell-centred primitives
+// (rho, u, U1, U2, U3, B1, B2, B3), layout [n1][n2][n3][8].
+struct SnapDesc {
+    const double* prims;
+    int n1, n2, n3;
+    double x1s, dx1, x2s, dx2, x3s, dx3;
+    double h, gam;
+    double rho_unit, B_unit;   // M_unit / L^3 and c sqrt(4 pi rho_unit)
+    double Rhigh, Rlow, sigma_cut, rmax;
+};
+
+// Trilinear interpolation at grid coordinates; clamped to the end cells in
+// x1 and x2, periodic in x3.
+KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, double P[8]) {
+    int i0[3], i1[3];
+    double d[3];
+    const double X0 = (x1 - s.x1s) / s.dx1 - 0.5, X1 = (x2 - s.x2s) / s.dx2 - 0.5;
+    const double Xv[2] = {X0, X1};
+    const int nn[2] = {s.n1, s.n2};
+    for (int k = 0; k < 2; ++k) {
+        const double f = floor(Xv[k]);
+        int i = (int)f;
+        double t = Xv[k] - f;
+        if (i < 0) { i = 0; t = 0.0; }
+        if (i > nn[k] - 2) { i = nn[k] - 2; t = 1.0; }
+        i0[k] = i;
+        i1[k] = i + 1;
+        d[k] = t;
+    }
+    {
+        const double X2 = (x3 - s.x3s) / s.dx3 - 0.5;
+        const double f = floor(X2);
+        long i = (long)f;
+        const long n = s.n3;
+        i = ((i % n) + n) % n;
+        i0[2] = (int)i;
+        i1[2] = (int)((i + 1) % n);
+        d[2] = X2 - f;
+    }
+    for (int q = 0; q < 8; ++q) P[q] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int ia = (c & 4) ? i1[0] : i0[0];
+        const int ib = (c & 2) ? i1[1] : i0[1];
+        const int ic = (c & 1) ? i1[2] : i0[2];
+        const double w = ((c & 4) ? d[0] : 1.0 - d[0]) * ((c & 2) ? d[1] : 1.0 - d[1]) *
+                         ((c & 1) ? d[2] : 1.0 - d[2]);
+        const double2* cell =
+            reinterpret_cast<const double2*>(s.prims + 8 * (((size_t)ia * s.n2 + ib) * s.n3 + ic));
+        const double2 v0 = cell[0], v1 = cell[1], v2 = cell[2], v3 = cell[3];
+        P[0] += w * v0.x; P[1] += w * v0.y; P[2] += w * v1.x; P[3] += w * v1.y;
+        P[4] += w * v2.x; P[5] += w * v2.y; P[6] += w * v3.x; P[7] += w * v3.y;
+    }
+}
+
+// Plasma from the snapshot.  The grid velocity and field components are
+// mapped to Kerr-Schild with the diagonal Jacobian (1, r, dtheta/dx2, 1);
+// then u^t = gamma / lapse, u^i = U^i - gamma lapse g^{ti} with
+// gamma = sqrt(1 + g_ij U^i U^j) and lapse = 1/sqrt(-g^tt); b^t = B^i u_i,
+// b^i = (B^i + b^t u^i) / u^t; T_i/T_e = (R_high beta^2 + R_low)/(1 + beta^2)
+// with beta = (gamma_ad - 1) u / (b.b/2); no emission (n_e = 0) where
+// b.b/rho > sigma_cut or r > r_emit_max.
+KRT_HD bool snapshot_plasma(const SnapDesc& s, double a, double m, double r, double th, double ph,
+                            const Metric& g, Plasma& p) {
+    const double x1 = log(r);
+    double x2 = th * (1.0 / kPi);
+    const double hh = 0.5 * (1.0 - s.h);
+    for (int it = 0; it < 8; ++it) {
+        double sn, cs;
+        sincos(2.0 * kPi * x2, &sn, &cs);
+        x2 -= (kPi * x2 + hh * sn - th) / (kPi * (1.0 + (1.0 - s.h) * cs));
+    }
+    double P[8];
+    snapshot_interp(s, x1, x2, ph, P);
+    const double rho = P[0], uu = P[1];
+    const double J2 = kPi * (1.0 + (1.0 - s.h) * cos(2.0 * kPi * x2));
+    const double U[4] = {0.0, P[2] * r, P[3] * J2, P[4]};
+    const double Bv[4] = {0.0, P[5] * r, P[6] * J2, P[7]};
+    // g_ij U^i U^j (spatial part)
+    const double q = g.rr * U[1] * U[1] + 2.0 * g.rp * U[1] * U[3] + g.hh * U[2] * U[2] + g.pp * U[3] * U[3];
+    const double gamma = sqrt(1.0 + q);
+    const double lapse = 1.0 / sqrt(-g.Itt);
+    p.u[0] = gamma / lapse;
+    p.u[1] = U[1] - gamma * lapse * g.Itr;
+    p.u[2] = U[2];
+    p.u[3] = U[3];
+    double ul[4];
+    lower(g, p.u, ul);
+    const double bt = Bv[1] * ul[1] + Bv[2] * ul[2] + Bv[3] * ul[3];
+    const double iut = 1.0 / p.u[0];
+    p.b[0] = bt;
+    p.b[1] = (Bv[1] + bt * p.u[1]) * iut;
+    p.b[2] = (Bv[2] + bt * p.u[2]) * iut;
+    p.b[3] = (Bv[3] + bt * p.u[3]) * iut;
+    const double bsq = dot(g, p.b, p.b);
+    p.B = sqrt(bsq > 0.0 ? bsq : 0.0) * s.B_unit;
+    p.ne = rho * s.rho_unit / (kMP + kME);
+    double thetae = 0.0;
+    if (rho > 0.0 && uu > 0.0) {
+        const double ib = 0.5 * bsq / ((s.gam - 1.0) * uu);
+        const double ib2 = ib * ib;
+        const double trat = (s.Rhigh + s.Rlow * ib2) / (1.0 + ib2);
+        thetae = (kMP / kME) * (s.gam - 1.0) * (uu / rho) / (1.0 + trat);
+    }
+    p.thetae = thetae;
+    if (!(rho > 0.0) || bsq / rho > s.sigma_cut || r > s.rmax) p.ne = 0.0;
+    (void)a;
+    (void)m;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Bessel-function ratios K0/K2 and K1/K2 of x = 1/Theta_e.
 // Table: piecewise Chebyshev series in t = ln x over [ln 1e-8, ln 700],

@@ -26,6 +26,7 @@ struct TraceArgs {
     int max_steps;
     int model;
     AdafDesc adaf;
+    SnapDesc snap;
     const double* btab;
     // path store of the wave-synchronous kernel
     double* pool;
@@ -120,8 +121,9 @@ struct XferState {
     double Dnext;
 };
 
-KRT_HD bool plasma_at(const TraceArgs& A, double r, double th, double ph,
-                                          const Metric& g, Plasma& p) {
+KRT_HD bool plasma_at(const TraceArgs& A, double r, double th, double ph, const Metric& g,
+                      Plasma& p) {
+    if (A.model == kModelSnapshot) return snapshot_plasma(A.snap, A.cam.a, A.cam.m, r, th, ph, g, p);
     return adaf_plasma(A.adaf, A.cam.a, A.cam.m, r, g, p);
 }
 

@@ -180,10 +180,25 @@ class Context:
                  int(d.get("field_geom", 0)))
         self._check(lib().krt_set_model_adaf(self.h, ctypes.byref(m)))
 
-    def set_model(self, d):
+    def set_model_snapshot(self, desc, prims):
+        """desc: snapshot description dict; prims: float64 [n1][n2][n3][8] device
+        tensor, borrowed (keep it alive while the model is in use)."""
+        _dev(prims, self.device)
+        if prims.dtype != torch.float64 or tuple(prims.shape) != (desc["n1"], desc["n2"], desc["n3"], 8):
+            raise ValueError("prims must be float64 [n1][n2][n3][8]")
+        d = SnapshotDesc()
+        d.struct_size = ctypes.sizeof(SnapshotDesc)
+        for name, _ in SnapshotDesc._fields_[1:]:
+            setattr(d, name, desc.get(name, 0))
+        self._snapshot = prims
+        self._check(lib().krt_set_model_snapshot(self.h, ctypes.byref(d), _ptr(prims), 0))
+
+    def set_model(self, d, prims=None):
         kind = int(d.get("kind", 0))
         if kind == 0:
             return self.set_model_adaf(d)
+        if kind == 3:
+            return self.set_model_snapshot(d, prims)
         raise ValueError(f"unsupported model kind {kind}")
 
     def trace(self, cam, stokes=None, status=None, nsteps=None, stats=True):

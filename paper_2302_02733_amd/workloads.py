@@ -60,3 +60,64 @@ def pixel_sample(nx, ny, count, seed):
     rng = np.random.default_rng(seed)
     count = min(count, nx * ny)
     return np.sort(rng.choice(nx * ny, size=count, replace=False)).astype(np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Synthetic GRMHD-like snapshot on a modified Kerr-Schild grid: a torus
+# profile with seeded power-law Gaussian random fluctuations (a stand-in for
+# the paper's GRMHD slice, which is not available).  Primitives (rho, u, U1,
+# U2, U3, B1, B2, B3) in code units, layout [n1][n2][n3][8].
+# ---------------------------------------------------------------------------
+
+def snapshot_desc(n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=0.3, M_unit_g=10 ** 18.5,
+                  R_high=40.0, R_low=1.0, sigma_cut=1.0, r_emit_max=50.0, gamma_ad=13.0 / 9.0):
+    import math
+    return {
+        "n1": n1, "n2": n2, "n3": n3,
+        "x1_start": math.log(r_in), "dx1": (math.log(r_out) - math.log(r_in)) / n1,
+        "x2_start": 0.0, "dx2": 1.0 / n2, "x3_start": 0.0, "dx3": 2.0 * math.pi / n3,
+        "hslope": hslope, "gamma_ad": gamma_ad, "M_unit_g": M_unit_g, "R_high": R_high,
+        "R_low": R_low, "sigma_cut": sigma_cut, "r_emit_max": r_emit_max,
+    }
+
+
+def _gaussian_field(shape, rng, slope=-11.0 / 3.0):
+    """Periodic zero-mean unit-variance Gaussian random field with power
+    spectrum P(k) ~ k^slope on the index grid (slope -11/3: Kolmogorov)."""
+    import numpy as np
+    k = [np.fft.fftfreq(n) * n for n in shape]
+    K2 = k[0][:, None, None] ** 2 + k[1][None, :, None] ** 2 + k[2][None, None, :] ** 2
+    amp = np.zeros_like(K2)
+    nz = K2 > 0
+    amp[nz] = K2[nz] ** (slope / 4.0)
+    noise = rng.standard_normal(shape)
+    f = np.fft.ifftn(np.fft.fftn(noise) * amp).real
+    f -= f.mean()
+    return f / f.std()
+
+
+def make_snapshot(desc, seed=7, a=0.94):
+    """Seeded synthetic snapshot for `desc`; returns float64 [n1][n2][n3][8]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = desc["n1"], desc["n2"], desc["n3"]
+    x1 = desc["x1_start"] + (np.arange(n1) + 0.5) * desc["dx1"]
+    x2 = desc["x2_start"] + (np.arange(n2) + 0.5) * desc["dx2"]
+    h = desc["hslope"]
+    r = np.exp(x1)[:, None, None]
+    th = (np.pi * x2 + 0.5 * (1 - h) * np.sin(2 * np.pi * x2))[None, :, None]
+    rh = 1.0 + np.sqrt(1.0 - a * a)
+    rho = np.exp(-(r - 15.0) ** 2 / (2 * 6.0 ** 2) - np.cos(th) ** 2 / (2 * 0.3 ** 2)) + 1e-4 * (r / 15.0) ** -1.5
+    uu = 0.2 * rho / r
+    d = [_gaussian_field((n1, n2, n3), rng) for _ in range(5)]
+    P = np.zeros((n1, n2, n3, 8))
+    P[..., 0] = rho * np.exp(0.5 * d[0] - 0.125)
+    P[..., 1] = uu * np.exp(0.5 * d[1] - 0.125)
+    vK = 1.0 / (r ** 1.5 + a)                                   # angular-velocity scale
+    P[..., 2] = (-0.02 / np.sqrt(r) + 0.05 * np.sqrt(1.0 / r) * d[2]) / r      # U1 (per unit x1)
+    P[..., 3] = 0.05 * vK * d[3] / np.pi                        # U2 (per unit x2)
+    P[..., 4] = vK * np.ones_like(d[4])                          # U3 (angular)
+    btor = np.sqrt(2 * (desc["gamma_ad"] - 1) * uu / 10.0)
+    P[..., 5] = 0.1 * np.sign(np.cos(th)) * (rh / r) ** 2 / r * (1 + 0.3 * d[4])
+    P[..., 7] = btor / (r * np.maximum(np.sin(th), 1e-3)) * (1 + 0.3 * d[4])
+    return np.ascontiguousarray(P)
