@@ -247,6 +247,47 @@ __device__ __forceinline__ void account(const TraceArgs& A, bool valid, uint8_t 
     }
 }
 
+// Transfer phase of one 8x8 tile (all lanes on the same point index, far
+// end first), output and accounting.
+__device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot, int lane,
+                                               bool valid, int pix, double alpha, double beta,
+                                               uint8_t st, int n) {
+    {
+        if (valid && st == kOverflow) {
+            const unsigned k = atomicAdd(A.overflow_count, 1u);
+            A.overflow_list[k] = pix;
+        }
+        account(A, valid, st, n);
+
+        // ---- transfer: all lanes on the same point index, far end first ----
+        const bool xfer = valid && st != kOverflow;
+        // a path ending in a non-finite point is transferred over its finite points
+        const int n_end = xfer ? ((st == kNonFinite) ? n - 1 : n) : -1;
+        int nred = n_end;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int o = __shfl_xor(nred, off);
+            nred = o > nred ? o : nred;
+        }
+        const int nmax = __builtin_amdgcn_readfirstlane(nred);
+        XferState xs;
+        Coh N;
+        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
+        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+        for (int m = nmax; m >= 0; --m) {
+            if (m <= n_end) {
+                double pt[8];
+                load_point(slot + ((size_t)m * 64 + lane) * 8, pt);
+                transfer_point(A, pt, m, m == n_end, xs, N);
+            }
+        }
+        if (xfer) {
+            double S[4];
+            camera_output(A, alpha, beta, N, S);
+            write_pixel(A, pix, S, st, n);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Persistent wave-synchronous tracer.  kGeoOnly: geodesic phase only, writing
 // the end state (no store, no transfer).
@@ -257,9 +298,11 @@ __global__ __launch_bounds__(256) void trace_waves(TraceArgs A) {
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
     for (;;) {
-        int batch = 0;
-        if (lane == 0) batch = (int)atomicAdd(A.queue, 1u);
-        batch = __shfl(batch, 0);
+        // One queue ticket per wave, taken without a lane-divergent branch:
+        // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
+        // as a scalar, so the loop exit below is wave-uniform.
+        const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
+        const int batch = __builtin_amdgcn_readfirstlane((int)ticket);
         if (batch >= A.nbatch) break;
         const int i = (batch % A.tiles_x) * 8 + (lane & 7);
         const int j = (batch / A.tiles_x) * 8 + (lane >> 3);
@@ -299,39 +342,8 @@ __global__ __launch_bounds__(256) void trace_waves(TraceArgs A) {
                 if (A.nsteps) A.nsteps[pix] = n;
             }
             account(A, valid, st, n);
-            continue;
-        }
-
-        if (valid && st == kOverflow) {
-            const unsigned k = atomicAdd(A.overflow_count, 1u);
-            A.overflow_list[k] = pix;
-        }
-        account(A, valid, st, n);
-
-        // ---- transfer: all lanes on the same point index, far end first ----
-        const bool xfer = valid && st != kOverflow;
-        // a path ending in a non-finite point is transferred over its finite points
-        const int n_end = xfer ? ((st == kNonFinite) ? n - 1 : n) : -1;
-        int nmax = n_end;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int o = __shfl_xor(nmax, off);
-            nmax = o > nmax ? o : nmax;
-        }
-        XferState xs;
-        Coh N;
-        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
-        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
-        for (int m = nmax; m >= 0; --m) {
-            if (m <= n_end) {
-                double pt[8];
-                load_point(slot + ((size_t)m * 64 + lane) * 8, pt);
-                transfer_point(A, pt, m, m == n_end, xs, N);
-            }
-        }
-        if (xfer) {
-            double S[4];
-            camera_output(A, alpha, beta, N, S);
-            write_pixel(A, pix, S, st, n);
+        } else {
+            trace_transfer(A, slot, lane, valid, pix, alpha, beta, st, n);
         }
     }
 }

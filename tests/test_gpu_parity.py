@@ -30,13 +30,21 @@ def ctx():
     c.close()
 
 
+def _log(msg):
+    import sys
+    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+
+
 def _gpu_image(ctx, w, nsteps=True):
+    cam = w["camera"]
+    _log(f"trace {cam['nx']}x{cam['ny']} max_steps={cam['max_steps']} cap={os.environ.get('KRT_PATH_CAP', 'default')}")
     ctx.set_units(w["units"])
     ctx.set_model(w["model"])
     cam = w["camera"]
     ns = torch.empty((cam["ny"], cam["nx"]), dtype=torch.int32, device=ctx.device) if nsteps else None
     out = ctx.trace(cam, nsteps=ns)
     torch.cuda.synchronize()
+    _log(f"trace done: {out['stats']}")
     return out
 
 
@@ -123,10 +131,12 @@ def test_adaf_plasma(ctx):
 
 def test_geodesic_end_states(ctx):
     cam = W.adaf_camera(32)
+    _log("geodesic_only 32x32")
     ctx.set_units(W.UNITS)
     ctx.set_model(W.ADAF)
     end, ns, st = ctx.geodesic_only(cam)
     end, ns, st = end.cpu().numpy(), ns.cpu().numpy(), st.cpu().numpy()
+    _log("geodesic_only done")
     for j in range(0, 32, 3):
         for i in range(0, 32, 3):
             al, be = oracle.pixel_position(cam, i, j)
