@@ -261,8 +261,9 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
 
         // ---- transfer: all lanes on the same point index, far end first ----
         const bool xfer = valid && st != kOverflow;
-        // a path ending in a non-finite point is transferred over its finite points
-        const int n_end = xfer ? ((st == kNonFinite) ? n - 1 : n) : -1;
+        // a path whose last point is non-finite or has crossed the polar axis
+        // (outside the coordinate chart) is transferred over the points before it
+        const int n_end = xfer ? ((st == kNonFinite || st == kAxis) ? n - 1 : n) : -1;
         int nred = n_end;
         for (int off = 32; off >= 1; off >>= 1) {
             const int o = __shfl_xor(nred, off);
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
             store_point(path + (size_t)n * 8, y, h);
             st = stop_test(A, y, h, n);
         }
-        const int n_end = (st == kNonFinite) ? n - 1 : n;
+        const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
         XferState xs;
         Coh N;
         for (int m = n_end; m >= 0; --m) {

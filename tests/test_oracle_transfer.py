@@ -198,3 +198,21 @@ def test_reducer_matches_fsum(small_image):
     f2, _ = oracle.reduce(cam2, units, x)
     dOm2 = (cam2["fov_x"] * L / (4 * units["dist_cm"])) * (cam2["fov_y"] * L / units["dist_cm"])
     assert f2[0] == pytest.approx(1e23 * dOm2 * 2.0, rel=1e-15)
+
+
+def test_axis_crossing_ray_is_transferred_before_the_crossing():
+    """a = 0, alpha = 0: the ray lies in a meridian plane and its last RK4 step
+    jumps across the polar axis (theta < 0); the image uses the points before
+    that step, so the pixel stays realizable."""
+    cam2 = W.adaf_camera(1, a=0.0, jitter=0)
+    for beta in (3.0, 9.0):
+        path, st = oracle.trace_ray(cam2, 0.0, beta)
+        assert st == oracle.AXIS and np.sin(path[-1, 1]) < 0
+        S = oracle.transfer_path(cam2, W.UNITS, W.ADAF, 0.0, beta, path[:-1])
+        assert S[0] > 0 and S[0] ** 2 >= S[1] ** 2 + S[2] ** 2 + S[3] ** 2
+    # the whole-image driver applies the same rule: 1x1 image through that pixel
+    cam3 = dict(cam2, nx=1, ny=2, fov_x=1e-12, fov_y=18.0)   # pixel centres at beta = -4.5, 4.5
+    Simg, st3, _ = oracle.render(cam3, W.UNITS, W.ADAF)
+    assert st3[1, 0] == oracle.AXIS
+    Sref = oracle.transfer_path(cam2, W.UNITS, W.ADAF, 0.0, 4.5, oracle.trace_ray(cam2, 0.0, 4.5)[0][:-1])
+    np.testing.assert_allclose(Simg[:, 1, 0], Sref, rtol=1e-12)
