@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="adaf1024", choices=["adaf64", "adaf1024", "adaf4096"])
-    ap.add_argument("--cpu-sample", type=int, default=1024, help="pixels for the oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="pixels for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--flop-probe", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")

@@ -171,8 +171,8 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
 // Sizes the wave-synchronous store: one slice of `cap` points for every
 // wavefront of the persistent grid (as many blocks as fit on the device).
 krt_status ensure_pool(krt_ctx* ctx) {
-    const int cap = env_int("KRT_PATH_CAP", 4096);
-    const double budget_gb = (double)env_int("KRT_POOL_GB", 48);
+    const int cap = env_int("KRT_PATH_CAP", 8192);
+    const double budget_gb = (double)env_int("KRT_POOL_GB", 64);
     int per_cu = 0;
     KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<false>, 256, 0));
     if (per_cu < 1) per_cu = 1;
