@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 # rocprofv3 FP64 VALU instruction counters on a divergence-free launch
 # (bench.py --flop-probe, every lane tracing the same ray), 64 lanes per wave
 # instruction.  See the design doc (measurement).
-FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "0")) or None
+FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "4128.9"))
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 HBM_PEAK_GBS = 8000.0
 
