@@ -53,15 +53,16 @@ def run_probe(kind):
                       "kernel_ms": out["stats"]["kernel_ms"]}))
 
 
-def cpu_baseline(w, sample):
+def cpu_baseline(w, sample, snap_host=None):
     import numpy as np
     import oracle
     from paper_2302_02733_amd import workloads as W
     cam = w["camera"]
     pix = W.pixel_sample(cam["nx"], cam["ny"], sample, 7)
     threads = oracle.max_threads()
+    snap = oracle.SnapshotHandle(w["snapshot"][0], snap_host) if snap_host is not None else None
     t0 = time.perf_counter()
-    S, st, ns = oracle.render(cam, w["units"], w["model"], pixels=pix, threads=threads)
+    S, st, ns = oracle.render(cam, w["units"], w["model"], snap=snap, pixels=pix, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": len(pix) / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(pix)} seeded pixels (seed 7) of the {cam['nx']}x{cam['ny']} image, "
@@ -73,7 +74,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="adaf1024", choices=["adaf64", "adaf1024", "adaf4096"])
+    ap.add_argument("--workload", default="adaf1024",
+                    choices=["adaf64", "adaf1024", "adaf4096", "snap48", "snap2048"])
     ap.add_argument("--cpu-sample", type=int, default=4096, help="pixels for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--flop-probe", action="store_true")
@@ -97,9 +99,17 @@ def main():
     dev = torch.device("cuda", 0)
     stokes = torch.empty((4, cam["ny"], cam["nx"]), dtype=torch.float64, device=dev)
     status = torch.empty((cam["ny"], cam["nx"]), dtype=torch.uint8, device=dev)
+    prims = snap_host = None
+    if "snapshot" in w:
+        desc, seed = w["snapshot"]
+        snap_host = W.make_snapshot(desc, seed)
+        prims = torch.tensor(snap_host, device=dev)
     with krt.Context(0) as ctx:
         ctx.set_units(w["units"])
-        ctx.set_model(w["model"])
+        if prims is not None:
+            ctx.set_model_snapshot(w["snapshot"][0], prims)
+        else:
+            ctx.set_model(w["model"])
         for _ in range(args.warmup):
             ctx.trace(cam, stokes=stokes, status=status)
             ctx.reduce(stokes, cam)
@@ -138,7 +148,9 @@ def main():
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "model": "analytic ADAF (a=0.9375, 60 deg, 230 GHz)",
+        "config": {"workload": args.workload,
+                   "model": ("analytic ADAF (a=0.9375, 60 deg, 230 GHz)" if prims is None else
+                             "synthetic GRMHD-like snapshot 288x128x128 (a=0.94, 20 deg, 230 GHz)"),
                    "pixels": npix, "eps": cam["eps"], "max_steps": cam["max_steps"],
                    "parallelism": "single GPU"},
         "ray_steps_per_s": ray_steps / (ms_per_step * 1e-3),
@@ -148,7 +160,7 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, snap_host)
     print(json.dumps(line))
 
 

@@ -29,18 +29,36 @@ def adaf_camera(n, *, jitter=1, seed=1, eps=0.01, max_steps=50000, a=0.9375, inc
     }
 
 
+def snapshot_camera(n, *, incl_deg=20.0, a=0.94, freq_hz=230e9, eps=0.01, max_steps=50000,
+                    fov=40.0, r_cam=1000.0, jitter=0, seed=0):
+    """Camera of the snapshot workloads (n x n pixels, no jitter by default)."""
+    return {
+        "a": a, "incl_deg": incl_deg, "phi_deg": 0.0, "r_cam": r_cam,
+        "fov_x": fov, "fov_y": fov, "nx": n, "ny": n, "freq_hz": freq_hz, "eps": eps,
+        "max_steps": max_steps, "jitter": jitter, "seed": seed, "mass_factor": 1,
+    }
+
+
 def workload(name):
-    """Named workloads: returns dict(camera=..., model=..., units=...)."""
+    """Named workloads: returns dict(camera=..., model=..., units=...) and, for
+    snapshot workloads, snapshot=(desc, seed) to be built by make_snapshot."""
     table = {
         # small ADAF image: 64 x 64, the oracle finishes it in seconds
-        "adaf64": (adaf_camera(64), ADAF),
+        "adaf64": (adaf_camera(64), ADAF, None),
         # plain method at scale
-        "adaf1024": (adaf_camera(1024), ADAF),
-        "adaf4096": (adaf_camera(4096), ADAF),
+        "adaf1024": (adaf_camera(1024), ADAF, None),
+        "adaf4096": (adaf_camera(4096), ADAF, None),
+        # GRMHD-like snapshot 288 x 128 x 128 seen at 20 degrees, 2048 x 2048
+        "snap2048": (snapshot_camera(2048), {"kind": 3}, (snapshot_desc(), 7)),
+        # small snapshot case for full-image parity
+        "snap48": (snapshot_camera(48), {"kind": 3}, (snapshot_desc(48, 32, 32), 7)),
     }
-    cam, model = table[name]
-    return {"camera": copy.deepcopy(cam), "model": copy.deepcopy(model),
-            "units": copy.deepcopy(UNITS)}
+    cam, model, snap = table[name]
+    out = {"camera": copy.deepcopy(cam), "model": copy.deepcopy(model),
+           "units": copy.deepcopy(UNITS)}
+    if snap is not None:
+        out["snapshot"] = (copy.deepcopy(snap[0]), snap[1])
+    return out
 
 
 def flat_camera(nx=2, ny=2, fov=8.0, r_cam=1000.0, incl_deg=90.0, eps=0.01, freq_hz=230e9,

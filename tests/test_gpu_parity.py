@@ -225,7 +225,7 @@ def test_invalid_camera_rejected_before_launch(ctx):
     assert e.value.code == krt.E_INVAL
 
 
-@pytest.mark.parametrize("n", [1024])
+@pytest.mark.parametrize("n", [1024, 4096])
 def test_full_size_sampled_parity(ctx, n):
     """The bench workload (ADAF, n x n) in the bench's launch configuration,
     checked on a seeded sample of pixels the oracle computes one by one."""
@@ -245,3 +245,82 @@ def test_full_size_sampled_parity(ctx, n):
     assert np.all(I >= 0)
     assert np.all(I * I * (1 + 1e-12) >= Q * Q + U * U + V * V)
     assert out["stats"]["rays"] == n * n == sum(out["stats"]["status_count"])
+
+
+# ---------------- snapshot model ----------------
+
+@pytest.fixture(scope="module")
+def snap48():
+    w = W.workload("snap48")
+    desc, seed = w["snapshot"]
+    P = W.make_snapshot(desc, seed)
+    return w, desc, P
+
+
+def _set_snapshot(ctx, w, desc, P):
+    t = torch.tensor(P, device=ctx.device)
+    ctx.set_units(w["units"])
+    ctx.set_model_snapshot(desc, t)
+    return t
+
+
+def test_snapshot_plasma(ctx, snap48):
+    w, desc, P = snap48
+    t = _set_snapshot(ctx, w, desc, P)
+    rng = np.random.default_rng(21)
+    n = 400
+    a = w["camera"]["a"]
+    X = np.stack([np.exp(rng.uniform(np.log(1.3), np.log(1100), n)), rng.uniform(0.01, np.pi - 0.01, n),
+                  rng.uniform(-20, 20, n)], 1)
+    out = ctx.plasma_eval(torch.tensor(X, device=ctx.device), a, 1).cpu().numpy()
+    h = oracle.SnapshotHandle(desc, P)
+    Lcm = 6.67430e-8 * w["units"]["M_bh_g"] / 2.99792458e10 ** 2
+    for k in range(n):
+        p = oracle.plasma({"kind": oracle.MODEL_SNAPSHOT}, a, 1.0, *X[k], Lcm, snap=h)
+        ref = np.concatenate([[p["ne"], p["thetae"], p["B"]], p["u"], p["b"]])
+        np.testing.assert_allclose(out[k, :3], ref[:3], rtol=1e-12, atol=1e-300)
+        scale = np.abs(ref[3:]).max()
+        assert np.abs(out[k, 3:11] - ref[3:]).max() <= 1e-12 * scale
+    del t
+
+
+def test_snapshot_image_parity(ctx, snap48):
+    w, desc, P = snap48
+    t = _set_snapshot(ctx, w, desc, P)
+    cam = w["camera"]
+    _log("snapshot trace 48x48")
+    ns = torch.empty((cam["ny"], cam["nx"]), dtype=torch.int32, device=ctx.device)
+    out = ctx.trace(cam, nsteps=ns)
+    torch.cuda.synchronize()
+    _log(f"trace done: {out['stats']}")
+    h = oracle.SnapshotHandle(desc, P)
+    So, sto, nso = oracle.render(cam, w["units"], w["model"], snap=h)
+    _compare_images(out["stokes"].cpu().numpy(), So, out["status"].cpu().numpy(), sto,
+                    ns.cpu().numpy(), nso)
+    del t
+
+
+def test_snapshot_full_size_sampled_parity(ctx):
+    """The 288x128x128 snapshot at 2048x2048 (the snapshot workload in the
+    bench's launch configuration), checked on sampled pixels."""
+    w = W.workload("snap2048")
+    desc, seed = w["snapshot"]
+    P = W.make_snapshot(desc, seed)
+    t = _set_snapshot(ctx, w, desc, P)
+    cam = w["camera"]
+    _log("snapshot trace 2048x2048")
+    ns = torch.empty((cam["ny"], cam["nx"]), dtype=torch.int32, device=ctx.device)
+    out = ctx.trace(cam, nsteps=ns)
+    torch.cuda.synchronize()
+    _log(f"trace done: {out['stats']}")
+    pix = W.pixel_sample(cam["nx"], cam["ny"], 64, 77)
+    h = oracle.SnapshotHandle(desc, P)
+    So, sto, nso = oracle.render(cam, w["units"], w["model"], snap=h, pixels=pix)
+    idx = torch.tensor(pix, device=ctx.device)
+    S = out["stokes"].reshape(4, -1)[:, idx].cpu().numpy()
+    assert np.array_equal(out["status"].reshape(-1)[idx].cpu().numpy(), sto)
+    assert np.array_equal(ns.reshape(-1)[idx].cpu().numpy(), nso)
+    assert np.abs(S - So).max() / np.abs(So[0]).max() < 1e-8
+    I, Q, U, V = out["stokes"].cpu().numpy()
+    assert np.all(I >= 0) and np.all(I * I * (1 + 1e-12) >= Q * Q + U * U + V * V)
+    del t
