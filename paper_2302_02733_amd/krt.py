@@ -10,7 +10,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkrt.so")
+# KRT_LIBRARY selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("KRT_LIBRARY") or os.path.join(_HERE, "libkrt.so")
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_STATE, E_UNSUPPORTED = range(6)
 RAY_ESCAPED, RAY_CAPTURED, RAY_STEP_CAP, RAY_NONFINITE, RAY_AXIS = range(5)
