@@ -66,6 +66,23 @@ def _compare_images(S, So, st=None, sto=None, ns=None, nso=None):
         assert np.abs(ns - nso).max() <= 2
 
 
+def _check_realizable(stokes):
+    """I >= 0 everywhere and I >= |P| up to the transport's truncation error:
+    each radiative update keeps a realizable Stokes vector exactly, but the
+    second-order (Heun) transport of the coherency matrix between points can
+    leave a nearly fully polarized pixel with |P|/I - 1 of order the scheme's
+    truncation error."""
+    I, Q, U, V = stokes.cpu().numpy()
+    assert np.all(I >= 0)
+    P = np.sqrt(Q * Q + U * U + V * V)
+    lit = I > 0
+    excess = float(np.max(P[lit] / I[lit] - 1.0)) if lit.any() else 0.0
+    _log(f"max |P|/I - 1 = {excess:.3e}, pixels with |P| > I: {int(np.sum(P > I))}")
+    assert excess <= 1e-6
+    ratio = np.where(lit, P / np.where(lit, I, 1.0), 0.0)
+    return int(np.argmax(ratio))
+
+
 # ---------------- components ----------------
 
 def test_bessel_ratios(ctx):
@@ -240,11 +257,13 @@ def test_full_size_sampled_parity(ctx, n):
     assert np.array_equal(ns, nso)
     scale = np.abs(So[0]).max()
     assert np.abs(S - So).max() / scale < 1e-8
-    # properties that hold at any size: realizability, non-negative I, status counts
-    I, Q, U, V = out["stokes"].cpu().numpy()
-    assert np.all(I >= 0)
-    assert np.all(I * I * (1 + 1e-12) >= Q * Q + U * U + V * V)
+    # properties that hold at any size: non-negative I, realizability, status counts
+    worst = _check_realizable(out["stokes"])
     assert out["stats"]["rays"] == n * n == sum(out["stats"]["status_count"])
+    # the most polarized pixel equals the oracle's value there
+    Sw, _, _ = oracle.render(w["camera"], w["units"], w["model"], pixels=np.array([worst]))
+    got = out["stokes"].reshape(4, -1)[:, worst].cpu().numpy()
+    assert np.abs(got - Sw[:, 0]).max() <= 1e-8 * abs(Sw[0, 0])
 
 
 # ---------------- snapshot model ----------------
@@ -321,6 +340,5 @@ def test_snapshot_full_size_sampled_parity(ctx):
     assert np.array_equal(out["status"].reshape(-1)[idx].cpu().numpy(), sto)
     assert np.array_equal(ns.reshape(-1)[idx].cpu().numpy(), nso)
     assert np.abs(S - So).max() / np.abs(So[0]).max() < 1e-8
-    I, Q, U, V = out["stokes"].cpu().numpy()
-    assert np.all(I >= 0) and np.all(I * I * (1 + 1e-12) >= Q * Q + U * U + V * V)
+    _check_realizable(out["stokes"])
     del t
