@@ -78,9 +78,12 @@ def _check_realizable(stokes):
     lit = I > 0
     excess = float(np.max(P[lit] / I[lit] - 1.0)) if lit.any() else 0.0
     _log(f"max |P|/I - 1 = {excess:.3e}, pixels with |P| > I: {int(np.sum(P > I))}")
-    assert excess <= 1e-6
     ratio = np.where(lit, P / np.where(lit, I, 1.0), 0.0)
-    return int(np.argmax(ratio))
+    return excess, int(np.argmax(ratio))
+
+
+# the transport's truncation error at eps = 0.01 (flat-space slab test: 1e-4 of I)
+P_EXCESS_TOL = 1e-4
 
 
 # ---------------- components ----------------
@@ -258,12 +261,13 @@ def test_full_size_sampled_parity(ctx, n):
     scale = np.abs(So[0]).max()
     assert np.abs(S - So).max() / scale < 1e-8
     # properties that hold at any size: non-negative I, realizability, status counts
-    worst = _check_realizable(out["stokes"])
+    excess, worst = _check_realizable(out["stokes"])
     assert out["stats"]["rays"] == n * n == sum(out["stats"]["status_count"])
     # the most polarized pixel equals the oracle's value there
     Sw, _, _ = oracle.render(w["camera"], w["units"], w["model"], pixels=np.array([worst]))
     got = out["stokes"].reshape(4, -1)[:, worst].cpu().numpy()
     assert np.abs(got - Sw[:, 0]).max() <= 1e-8 * abs(Sw[0, 0])
+    assert excess <= P_EXCESS_TOL
 
 
 # ---------------- snapshot model ----------------
@@ -340,5 +344,9 @@ def test_snapshot_full_size_sampled_parity(ctx):
     assert np.array_equal(out["status"].reshape(-1)[idx].cpu().numpy(), sto)
     assert np.array_equal(ns.reshape(-1)[idx].cpu().numpy(), nso)
     assert np.abs(S - So).max() / np.abs(So[0]).max() < 1e-8
-    _check_realizable(out["stokes"])
+    excess, worst = _check_realizable(out["stokes"])
+    Sw, _, _ = oracle.render(cam, w["units"], w["model"], snap=h, pixels=np.array([worst]))
+    got = out["stokes"].reshape(4, -1)[:, worst].cpu().numpy()
+    assert np.abs(got - Sw[:, 0]).max() <= 1e-8 * abs(Sw[0, 0])
+    assert excess <= P_EXCESS_TOL
     del t
