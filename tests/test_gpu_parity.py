@@ -73,7 +73,12 @@ def _check_realizable(stokes):
     leave a nearly fully polarized pixel with |P|/I - 1 of order the scheme's
     truncation error."""
     I, Q, U, V = stokes.cpu().numpy()
-    assert np.all(I >= 0)
+    neg = np.flatnonzero(I.ravel() < 0)
+    if neg.size:
+        k = neg[np.argmin(I.ravel()[neg])]
+        _log(f"{neg.size} pixels with I < 0; most negative: pixel {k}, I={I.ravel()[k]:.3e}, "
+             f"Q={Q.ravel()[k]:.3e}, U={U.ravel()[k]:.3e}, V={V.ravel()[k]:.3e}, I_max={I.max():.3e}")
+        return None, int(k)
     P = np.sqrt(Q * Q + U * U + V * V)
     lit = I > 0
     excess = float(np.max(P[lit] / I[lit] - 1.0)) if lit.any() else 0.0
@@ -263,11 +268,12 @@ def test_full_size_sampled_parity(ctx, n):
     # properties that hold at any size: non-negative I, realizability, status counts
     excess, worst = _check_realizable(out["stokes"])
     assert out["stats"]["rays"] == n * n == sum(out["stats"]["status_count"])
-    # the most polarized pixel equals the oracle's value there
-    Sw, _, _ = oracle.render(w["camera"], w["units"], w["model"], pixels=np.array([worst]))
+    # the most polarized (or most negative) pixel equals the oracle's value there
+    Sw, stw, nsw = oracle.render(w["camera"], w["units"], w["model"], pixels=np.array([worst]))
     got = out["stokes"].reshape(4, -1)[:, worst].cpu().numpy()
+    _log(f"pixel {worst}: gpu {got}, oracle {Sw[:, 0]}, status {stw[0]}, steps {nsw[0]}")
     assert np.abs(got - Sw[:, 0]).max() <= 1e-8 * abs(Sw[0, 0])
-    assert excess <= P_EXCESS_TOL
+    assert excess is not None and excess <= P_EXCESS_TOL
 
 
 # ---------------- snapshot model ----------------
@@ -345,8 +351,9 @@ def test_snapshot_full_size_sampled_parity(ctx):
     assert np.array_equal(ns.reshape(-1)[idx].cpu().numpy(), nso)
     assert np.abs(S - So).max() / np.abs(So[0]).max() < 1e-8
     excess, worst = _check_realizable(out["stokes"])
-    Sw, _, _ = oracle.render(cam, w["units"], w["model"], snap=h, pixels=np.array([worst]))
+    Sw, stw, nsw = oracle.render(cam, w["units"], w["model"], snap=h, pixels=np.array([worst]))
     got = out["stokes"].reshape(4, -1)[:, worst].cpu().numpy()
+    _log(f"pixel {worst}: gpu {got}, oracle {Sw[:, 0]}, status {stw[0]}, steps {nsw[0]}")
     assert np.abs(got - Sw[:, 0]).max() <= 1e-8 * abs(Sw[0, 0])
-    assert excess <= P_EXCESS_TOL
+    assert excess is not None and excess <= P_EXCESS_TOL
     del t
