@@ -79,7 +79,8 @@ typedef struct {
     double fov_x, fov_y; /* field of view (units of M), > 0                   */
     int32_t nx, ny;      /* resolution, >= 1                                  */
     double freq_hz;      /* observing frequency at the camera, > 0            */
-    double eps;          /* step parameter, 0 < eps <= 0.5                    */
+    double eps;          /* step parameter, 0 < eps <= 0.5: each step changes
+                            ln r, theta, ln sin(theta) and phi by about eps  */
     int32_t max_steps;   /* step cap per ray, >= 1                            */
     int32_t jitter;      /* 1: seeded jitter inside each pixel, 0: centres    */
     uint64_t seed;       /* jitter seed                                       */

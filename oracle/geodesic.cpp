@@ -7,8 +7,12 @@
  * the path is saved.  Sec. 2.2 names that parameter eps.  Readings:
  *  - state y = (X^mu, K^mu), dX/dlam = K, dK^mu/dlam = -Gamma^mu_ab K^a K^b;
  *  - classical fourth-order Runge-Kutta in lam, no error control;
- *  - step |dlam| = eps / (|K^r|/r + |K^theta| + |K^phi|) at the start of the
- *    step, dlam < 0;
+ *  - step |dlam| = eps / (|K^r|/r + |K^theta| max(1, |cot theta|) + |K^phi|)
+ *    at the start of the step, dlam < 0: the step bounds the relative change
+ *    of r, the change of theta and phi, and the relative change of sin(theta)
+ *    (d ln sin(theta) = cot(theta) dtheta), so a ray that passes close to the
+ *    polar axis, where the coordinate frame turns quickly, takes steps that
+ *    shrink with its distance to the axis;
  *  - after each step, stop on (in this order) a non-finite component,
  *    sin(theta) < 1e-12, r < 1.05 r_+ (flat space: r < 1e-6), r > r_cam while
  *    moving outward, or the step cap;
@@ -64,7 +68,9 @@ int trace(const or_camera* cam, const double X0[4], const double K0[4],
             *status = OR_STEP_CAP;
             return -2;
         }
-        double h = -cam->eps / (std::fabs(y[5]) / y[1] + std::fabs(y[6]) + std::fabs(y[7]));
+        double cot = std::cos(y[2]) / std::sin(y[2]);
+        double h = -cam->eps / (std::fabs(y[5]) / y[1] + std::fabs(y[6]) * std::fmax(1.0, std::fabs(cot)) +
+                                std::fabs(y[7]));
         double k1[8], k2[8], k3[8], k4[8], yt[8];
         rhs(a, m, y, k1);
         for (int i = 0; i < 8; ++i) yt[i] = y[i] + 0.5 * h * k1[i];

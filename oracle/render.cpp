@@ -6,9 +6,8 @@
  * OpenMP threads; the product is one fully polarized image (Table 1 caption:
  * Stokes I, Q, U, V).  Per pixel: camera launch, backward geodesic saved in
  * full, forward transfer along it.  A ray whose last point is non-finite, or
- * has crossed the polar axis (theta outside (0, pi), where the spherical
- * coordinates no longer describe the point), is transferred over the points
- * before that one; a pixel whose Stokes vector comes out non-finite is
+ * lies on the polar axis (sin(theta) < 1e-12, where the spherical coordinate
+ * frame is singular), is transferred over the points before that one; a pixel whose Stokes vector comes out non-finite is
  * written as zeros with status NONFINITE.
  *
  * Reduction: F_S = 1e23 dOmega sum S_ij (Jy), dOmega = (fov_x L/(nx D))
@@ -59,8 +58,8 @@ int or_render(const or_camera* cam, const or_units* units, const or_model* model
         std::vector<double> path;
         int32_t n_end = 0, st = 0;
         trace(cam, X, K, path, cam->max_steps, &n_end, &st);
-        /* the stopping point of a non-finite or axis-crossing ray lies outside
-         * the coordinate chart: transfer over the points before it */
+        /* the stopping point of a non-finite or axis ray lies where the
+         * coordinate frame fails: transfer over the points before it */
         int32_t n_use = (st == OR_NONFINITE || st == OR_AXIS) ? n_end - 1 : n_end;
         double ex[4], ey[4], S[4];
         screen_legs(cam, cf, alpha, beta, ex, ey);

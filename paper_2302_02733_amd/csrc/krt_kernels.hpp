@@ -62,10 +62,15 @@ KRT_HD void geo_rhs(double a, double m, const double y[7], double d[7]) {
     d[6] = acc[3];
 }
 
-// One classical RK4 step with |dlam| = eps / (|K^r|/r + |K^theta| + |K^phi|),
-// dlam < 0.  Returns dlam.
+// One classical RK4 step with
+//   |dlam| = eps / (|K^r|/r + |K^theta| max(1, |cot theta|) + |K^phi|),
+// dlam < 0: relative change of r, change of theta and phi, and relative change
+// of sin(theta) bounded by eps, so steps shrink near the polar axis where the
+// coordinate frame turns quickly.  Returns dlam.
 KRT_HD double rk4_step(double a, double m, double eps, double y[7]) {
-    const double h = -eps / (fabs(y[4]) / y[0] + fabs(y[5]) + fabs(y[6]));
+    double sn, cs;
+    sincos(y[1], &sn, &cs);
+    const double h = -eps / (fabs(y[4]) / y[0] + fabs(y[5]) * fmax(1.0, fabs(cs / sn)) + fabs(y[6]));
     double k1[7], k2[7], k3[7], k4[7], yt[7];
     geo_rhs(a, m, y, k1);
 #pragma unroll
@@ -261,8 +266,8 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
 
         // ---- transfer: all lanes on the same point index, far end first ----
         const bool xfer = valid && st != kOverflow;
-        // a path whose last point is non-finite or has crossed the polar axis
-        // (outside the coordinate chart) is transferred over the points before it
+        // a path whose last point is non-finite or lies on the polar axis (where
+        // the coordinate frame is singular) is transferred over the points before it
         const int n_end = xfer ? ((st == kNonFinite || st == kAxis) ? n - 1 : n) : -1;
         int nred = n_end;
         for (int off = 32; off >= 1; off >>= 1) {

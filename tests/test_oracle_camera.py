@@ -118,7 +118,7 @@ def test_flat_rays_are_straight_with_exact_impact_parameter(alpha, beta):
 
 def test_ray_through_the_polar_axis_stops_with_axis_status():
     """alpha = 0 at theta_o = 90 deg: the ray lies in a meridian plane and
-    crosses the coordinate axis, where sin(theta) < 1e-12 stops it."""
+    closes in on the coordinate axis, where sin(theta) < 1e-12 stops it."""
     path, st = oracle.trace_ray(W.flat_camera(), 0.0, 4.0)
     assert st == oracle.AXIS
     assert np.sin(path[-1, 1]) < 1e-12

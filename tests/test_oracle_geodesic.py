@@ -10,6 +10,9 @@
   R(r) = (r^2 + a^2 - a xi)^2 - Delta (eta + (xi - a)^2) has no root outside
   the horizon (xi = L/E, eta = Q/E^2); the oracle agrees away from the
   critical curve.
+- Step rule: no step changes ln r, theta, ln sin(theta) or phi by more than
+  about eps, also on a ray that grazes the polar axis (where the coordinate
+  frame turns fastest).
 """
 import numpy as np
 import pytest
@@ -128,3 +131,18 @@ def test_kerr_capture_matches_radial_potential():
     assert total > 0.9 * n * n
     assert agree == total
     assert 0 < (status == oracle.CAPTURED).sum() < n * n
+
+
+@pytest.mark.parametrize("which,alpha,beta", [
+    ("adaf", 0.0, 4.0), ("adaf", 0.3, 9.0), ("adaf", -5.0, 2.0),
+    ("snap", -0.3223, 11.0059),   # passes within sin(theta) ~ 1e-5 of the axis
+    ("snap", 2.0, -3.0),
+])
+def test_step_bounds_the_change_of_every_coordinate_scale(which, alpha, beta):
+    cam = W.adaf_camera(1, jitter=0) if which == "adaf" else W.workload("snap2048")["camera"]
+    path, st = oracle.trace_ray(cam, alpha, beta)
+    r, th, ph = path[:, 0], path[:, 1], path[:, 2]
+    for x in (np.log(r), th, np.log(np.abs(np.sin(th))), ph):
+        assert np.abs(np.diff(x)).max() <= 1.05 * cam["eps"]
+    if which == "snap" and alpha < 0:
+        assert np.sin(th).min() < 1e-4
