@@ -13,6 +13,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep packed-FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no hoisting of constants and uniform values out of the persistent loops
+    # into long-lived registers (the tracer is limited by register pressure)
+    "-mllvm", "-disable-machine-licm",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

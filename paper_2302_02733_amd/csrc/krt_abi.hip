@@ -130,6 +130,7 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     A.eps = cam->eps;
     A.r_stop = cam->mass_factor == 0 ? 1e-6 : 1.05 * horizon(cam->a, 1.0);
     A.L_cm = ctx->units_set ? kG * ctx->units.M_bh_g / (kC * kC) : 0.0;
+    A.fac0 = A.L_cm / cam->freq_hz;
     A.max_steps = cam->max_steps;
     A.model = ctx->model < 0 ? kModelAdaf : ctx->model;
     if (ctx->model == kModelSnapshot) {

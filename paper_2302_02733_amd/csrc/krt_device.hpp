@@ -49,9 +49,8 @@ struct MetricD {
     double tt, tr, tp, rr, rp, hh, pp;
 };
 
-KRT_HD void metric_eval(double a, double m, double r, double th, Metric& g) {
-    double s, c;
-    sincos(th, &s, &c);
+// Metric at (r, theta) given s = sin(theta), c = cos(theta).
+KRT_HD void metric_eval_sc(double a, double m, double r, double s, double c, Metric& g) {
     const double s2 = s * s;
     const double Sig = r * r + a * a * c * c;
     const double iS = 1.0 / Sig;
@@ -74,10 +73,16 @@ KRT_HD void metric_eval(double a, double m, double r, double th, Metric& g) {
     g.Ipp = iS / s2;
 }
 
-// Metric plus its r- and theta-derivatives.
-KRT_HD void metric_eval_d(double a, double m, double r, double th, Metric& g, MetricD& dr,
-                          MetricD& dh) {
-    metric_eval(a, m, r, th, g);
+KRT_HD void metric_eval(double a, double m, double r, double th, Metric& g) {
+    double s, c;
+    sincos(th, &s, &c);
+    metric_eval_sc(a, m, r, s, c, g);
+}
+
+// Metric plus its r- and theta-derivatives, given sin and cos of theta.
+KRT_HD void metric_eval_d_sc(double a, double m, double r, double sn, double cs, Metric& g,
+                             MetricD& dr, MetricD& dh) {
+    metric_eval_sc(a, m, r, sn, cs, g);
     const double s = g.s, c = g.c, s2 = s * s, sc = s * c;
     const double Sig = g.Sig, iS = 1.0 / Sig;
     const double f = g.tr;
@@ -100,6 +105,13 @@ KRT_HD void metric_eval_d(double a, double m, double r, double th, Metric& g, Me
     dh.rp = -a * (s2_h * opf + s2 * f_h);
     dh.hh = Sig_h;
     dh.pp = s2_h * (Sig + a * a * s2 * opf) + s2 * (Sig_h + a * a * (s2_h * opf + s2 * f_h));
+}
+
+KRT_HD void metric_eval_d(double a, double m, double r, double th, Metric& g, MetricD& dr,
+                          MetricD& dh) {
+    double s, c;
+    sincos(th, &s, &c);
+    metric_eval_d_sc(a, m, r, s, c, g, dr, dh);
 }
 
 // Lower a vector: v_mu = g_{mu nu} v^nu.
@@ -135,11 +147,11 @@ KRT_HD void dmetric_times(const MetricD& d, const double K[4], double o[4]) {
 // Geodesic acceleration dK^mu/dlam = -Gamma^mu_ab K^a K^b, written as
 // -g^{mu nu} [K^r (D_r K)_nu + K^h (D_h K)_nu - 1/2 delta_nu^{r,h} K.D K]
 // (only r and theta derivatives are non-zero).
-KRT_HD void geodesic_acc(double a, double m, double r, double th, const double K[4],
-                         double acc[4]) {
+KRT_HD void geodesic_acc_sc(double a, double m, double r, double sn, double cs, const double K[4],
+                            double acc[4]) {
     Metric g;
     MetricD dr, dh;
-    metric_eval_d(a, m, r, th, g, dr, dh);
+    metric_eval_d_sc(a, m, r, sn, cs, g, dr, dh);
     double vr[4], vh[4];
     dmetric_times(dr, K, vr);
     dmetric_times(dh, K, vh);
@@ -152,6 +164,13 @@ KRT_HD void geodesic_acc(double a, double m, double r, double th, const double K
     double up[4];
     raise(g, w, up);
     for (int k = 0; k < 4; ++k) acc[k] = -up[k];
+}
+
+KRT_HD void geodesic_acc(double a, double m, double r, double th, const double K[4],
+                         double acc[4]) {
+    double s, c;
+    sincos(th, &s, &c);
+    geodesic_acc_sc(a, m, r, s, c, K, acc);
 }
 
 // Connection along the ray A^mu_b = Gamma^mu_ab K^a =
@@ -509,66 +528,68 @@ KRT_HD void bessel_ratios(const double* __restrict__ table, double x,
 // ---------------------------------------------------------------------------
 // Thermal synchrotron coefficients in the fluid frame (cgs): emissivities of
 // Dexter (2016, App. A) in the basis whose second leg is along the projected
-// field, Kirchhoff absorptivities, thermal rotativities.  Returns
-// (j_I, j_Q, j_V, a_I, a_Q, a_V, r_Q, r_V) and the source function
-// B_nu / nu^3 (Kirchhoff: j = alpha B_nu).
+// field, Kirchhoff absorptivities, thermal rotativities.  Writes
+// (j_I, j_Q, j_V, a_I, a_Q, a_V, r_Q, r_V) and returns the source function
+// B_nu / nu^3 = (2 h / c^2) / expm1(h nu / k T_e) where a_I > 0 (else 0).
+// Constant factors are folded and divisions shared: 1/Theta_e, 1/nu,
+// nu_c / nu, x^-1/3 and 1/B_nu are the only reciprocals.
 // ---------------------------------------------------------------------------
-KRT_HD void thermal_coefficients(const double* __restrict__ btab, double ne,
-                                                     double thetae, double B, double nu,
-                                                     double cth, double out[8]) {
+constexpr double kNuBPerB = kE / (2.0 * kPi * kME * kC);          // nu_B / B
+constexpr double kRhoVFac = 2.0 * kE * kE / (kME * kC);          // r_V prefactor
+constexpr double kJIFac = kE * kE / (2.0 * 1.7320508075688772 * kC);
+constexpr double kHnuOverTheta = kH / (kME * kC * kC);           // h nu / (k T_e) = this nu / Theta_e
+constexpr double kSrcFac = 2.0 * kH / (kC * kC);
+
+KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, double thetae,
+                                   double B, double nu, double cth, double out[8]) {
     for (int k = 0; k < 8; ++k) out[k] = 0.0;
-    if (!(ne > 0.0) || !(thetae > 0.0) || !(B > 0.0) || !(nu > 0.0)) return;
-    const double e2 = kE * kE;
+    if (!(ne > 0.0) || !(thetae > 0.0) || !(B > 0.0) || !(nu > 0.0)) return 0.0;
     cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
     const double sth = sqrt(1.0 - cth * cth);
-    const double nuB = kE * B / (2.0 * kPi * kME * kC);
+    const double nuB = kNuBPerB * B;
+    const double iTh = 1.0 / thetae;
     double k0k2, k1k2;
-    bessel_ratios(btab, 1.0 / thetae, k0k2, k1k2);
+    bessel_ratios(btab, iTh, k0k2, k1k2);
     const double inu = 1.0 / nu;
-    out[7] = 2.0 * ne * e2 * nuB * cth / (kME * kC) * inu * inu * k0k2;
-    if (sth < 1e-10) return;
+    const double inu2 = inu * inu;
+    out[7] = kRhoVFac * ne * nuB * cth * inu2 * k0k2;
+    if (sth < 1e-10) return 0.0;
+    out[6] = 0.5 * kRhoVFac * ne * nuB * nuB * sth * sth * inu2 * inu * (k1k2 + 6.0 * thetae);
 
     const double nuc = 1.5 * nuB * sth * thetae * thetae;
-    const double x = nu / nuc;
-    const double x13 = cbrt(x);
+    const double x13 = cbrt(nu / nuc);
     const double xm13 = 1.0 / x13;
     const double xm23 = xm13 * xm13;
     const double ex = exp(-1.8899 * x13);
     const double II = 2.5651 * (1.0 + 1.92 * xm13 + 0.9977 * xm23) * ex;
     const double IQ = 2.5651 * (1.0 + 0.93193 * xm13 + 0.499873 * xm23) * ex;
-    const double IV = (1.81348 / x + 3.42319 * xm23 + 0.0292545 / sqrt(x) + 2.03773 * xm13) * ex;
-    const double pre = ne * e2 * nu / (2.0 * 1.7320508075688772 * kC * thetae * thetae);
+    // x^-1 = xm13^3, x^-1/2 = xm13^(3/2)
+    const double IV = (1.81348 * xm23 * xm13 + 3.42319 * xm23 + 0.0292545 * xm13 * sqrt(xm13) +
+                       2.03773 * xm13) * ex;
+    const double pre = kJIFac * ne * nu * iTh * iTh;
     double jI = pre * II;
     double jQ = pre * IQ;
-    double jV = 2.0 * ne * e2 * nu * (cth / sth) / (3.0 * 1.7320508075688772 * kC * thetae * thetae * thetae) * IV;
+    // j_V = 2 ne e^2 nu cot(theta_B) IV / (3 sqrt3 c Theta^3) = pre (4/3) cot(theta_B) IV / Theta
+    double jV = pre * (4.0 / 3.0) * (cth / sth) * iTh * IV;
     const double jP = hypot(jQ, jV);
     if (jP > jI) {
         const double sc = jI / jP;
         jQ *= sc;
         jV *= sc;
     }
-    const double Te = thetae * kME * kC * kC / kKB;
-    const double Bnu = 2.0 * kH * nu * nu * nu / (kC * kC) / expm1(kH * nu / (kKB * Te));
-    double aI = 0.0, aQ = 0.0, aV = 0.0;
-    if (jI > 0.0 && Bnu > 0.0) {
-        aI = jI / Bnu;
-        aQ = jQ / Bnu;
-        aV = jV / Bnu;
-    }
     out[0] = jI;
     out[1] = jQ;
     out[2] = jV;
-    out[3] = aI;
-    out[4] = aQ;
-    out[5] = aV;
-    out[6] = ne * e2 * nuB * nuB * sth * sth / (kME * kC) * inu * inu * inu * (k1k2 + 6.0 * thetae);
-}
-
-// Invariant source function B_nu(T_e) / nu^3 = (2 h / c^2) / expm1(h nu / k T_e).
-KRT_HD double source_function(double thetae, double nu) {
-    if (!(thetae > 0.0)) return 0.0;
-    const double Te = thetae * kME * kC * kC / kKB;
-    return 2.0 * kH / (kC * kC) / expm1(kH * nu / (kKB * Te));
+    const double seq = kSrcFac / expm1(kHnuOverTheta * nu * iTh);
+    const double Bnu = seq * nu * nu * nu;
+    if (jI > 0.0 && Bnu > 0.0) {
+        const double iB = 1.0 / Bnu;
+        out[3] = jI * iB;
+        out[4] = jQ * iB;
+        out[5] = jV * iB;
+        return out[3] > 0.0 ? seq : 0.0;
+    }
+    return 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -594,6 +615,14 @@ KRT_HD void gen_apply(double AQ, double AV, double RQ, double RV, double w, cons
     o[3] = -w * (AV * v[0] - RQ * v[2]);
 }
 
+// 1/n! for n = 0..21 (correctly rounded).
+constexpr double kInvFact[22] = {
+    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333,
+    0.001388888888888889, 0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06,
+    2.755731922398589e-07, 2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10,
+    1.1470745597729725e-11, 7.647163731819816e-13, 4.779477332387385e-14, 2.8114572543455206e-15,
+    1.5619206968586225e-16, 8.22063524662433e-18, 4.110317623312165e-19, 1.9572941063391263e-20};
+
 KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double RQ, double RV,
                             double w, double S[4]) {
     const double tau = AI * w;
@@ -611,30 +640,24 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         Y = rad - q;
         X = (Y > 0.0) ? ar * ar / Y : 0.0;
     }
-    const double x = sqrt(X), y = sqrt(Y);
-    const double et = exp(-tau);
     double d0, omd0, d1, d2, d3;
     const double XY = X + Y;
     if (XY < 0.1) {
         // series in X and Z = -Y: c2 = sum_k h_k/(2k)!, c3 = sum_k h_k/(2k+1)!,
-        // c0 = 1 - X Z sum_{k>=2} h_{k-1}/(2k)!, c1 = 1 - X Z sum_{k>=2} h_{k-1}/(2k+1)!,
+        // c0 = 1 - X Z sum_{k>=1} h_k/(2k+2)!, c1 = 1 - X Z sum_{k>=1} h_k/(2k+3)!,
         // h_k = sum_{j<k} X^j Z^(k-1-j) (h_1 = 1, h_{k+1} = X h_k + Z^k).
+        const double et = exp(-tau);
         const double Z = -Y;
         double h = 1.0, zk = 1.0;
-        double fe = 2.0, fo = 6.0;  // (2k)!, (2k+1)! at k = 1
         double c2 = 0.0, c3 = 0.0, s0 = 0.0, s1 = 0.0;
+#pragma unroll
         for (int k = 1; k <= 9; ++k) {
-            c2 += h / fe;
-            c3 += h / fo;
-            // terms of c0, c1 use h_{k} with factorials of k+1
-            const double fe1 = fe * (2 * k + 1) * (2 * k + 2);
-            const double fo1 = fo * (2 * k + 2) * (2 * k + 3);
-            s0 += h / fe1;
-            s1 += h / fo1;
+            c2 += h * kInvFact[2 * k];
+            c3 += h * kInvFact[2 * k + 1];
+            s0 += h * kInvFact[2 * k + 2];
+            s1 += h * kInvFact[2 * k + 3];
             zk *= Z;
             h = X * h + zk;
-            fe = fe1;
-            fo = fo1;
         }
         const double XZ = X * Z;
         d0 = et * (1.0 - XZ * s0);
@@ -643,9 +666,13 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         d2 = et * c2;
         d3 = et * c3;
     } else {
-        const double ep = exp(x - tau), em = exp(-x - tau);
-        const double ch = 0.5 * (ep + em);                  // e^-tau cosh x
-        const double shx = (x > 1e-8) ? 0.5 * (ep - em) / x : et;   // e^-tau sinh x / x
+        const double x = sqrt(X), y = sqrt(Y);
+        // u = e^((x - tau)/2), v = e^(-(x + tau)/2): e^(x-tau) = u^2,
+        // e^(-x-tau) = v^2, e^-tau = u v
+        const double u = exp(0.5 * (x - tau)), v = exp(-0.5 * (x + tau));
+        const double ep = u * u, em = v * v, et = u * v;
+        const double ch = 0.5 * (ep + em);                              // e^-tau cosh x
+        const double shx = (x > 1e-8) ? 0.5 * (ep - em) / x : et;        // e^-tau sinh x / x
         double sy, cy;
         sincos(y, &sy, &cy);
         const double syy = (y > 1e-8) ? sy / y : 1.0;
@@ -654,10 +681,11 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         d1 = (Y * shx + X * et * syy) * iXY;
         d2 = (ch - et * cy) * iXY;
         d3 = (shx - et * syy) * iXY;
-        // e^-tau (1 - c0) = (2 X e^-tau sin^2(y/2) - 2 Y (e^-tau/2 sinh(x/2))^2) / (X + Y)
-        const double qh = 0.5 * (exp(0.5 * (x - tau)) - exp(-0.5 * (x + tau)));
-        const double snh = sin(0.5 * y);
-        omd0 = -expm1(-tau) + 2.0 * (X * et * snh * snh - Y * qh * qh) * iXY;
+        // e^-tau (1 - c0) = (2 X e^-tau sin^2(y/2) - 2 Y (e^-tau/2 sinh(x/2))^2) / (X + Y),
+        // sin^2(y/2) = sin^2 y / (2 (1 + cos y)) (cos y > 0) or (1 - cos y) / 2
+        const double qh = 0.5 * (u - v);
+        const double s2h = (cy > 0.0) ? sy * sy / (2.0 * (1.0 + cy)) : 0.5 * (1.0 - cy);
+        omd0 = -expm1(-tau) + 2.0 * (X * et * s2h - Y * qh * qh) * iXY;
     }
     double D[4] = {S[0] - Seq, S[1], S[2], S[3]};
     double T[4], U[4];

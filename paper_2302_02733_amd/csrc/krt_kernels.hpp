@@ -23,6 +23,7 @@ enum : int { kModelAdaf = 0, kModelSnapshot = 1 };
 struct TraceArgs {
     CameraDesc cam;
     double eps, r_stop, L_cm;
+    double fac0;        // L_cm / freq: path length unit over the camera frequency
     int max_steps;
     int model;
     AdafDesc adaf;
@@ -49,52 +50,71 @@ struct TraceArgs {
 // ---------------------------------------------------------------------------
 // Geodesic: state y = (r, theta, phi, K^t, K^r, K^theta, K^phi).
 // ---------------------------------------------------------------------------
-KRT_HD void geo_rhs(double a, double m, const double y[7], double d[7]) {
+// Derivative of the state at a point whose sin and cos of theta are given.
+KRT_HD void geo_rhs_sc(double a, double m, const double y[7], double sn, double cs, double d[7]) {
     d[0] = y[4];
     d[1] = y[5];
     d[2] = y[6];
     const double K[4] = {y[3], y[4], y[5], y[6]};
     double acc[4];
-    geodesic_acc(a, m, y[0], y[1], K, acc);
+    geodesic_acc_sc(a, m, y[0], sn, cs, K, acc);
     d[3] = acc[0];
     d[4] = acc[1];
     d[5] = acc[2];
     d[6] = acc[3];
 }
 
+KRT_HD void geo_rhs(double a, double m, const double y[7], double d[7]) {
+    double sn, cs;
+    sincos(y[1], &sn, &cs);
+    geo_rhs_sc(a, m, y, sn, cs, d);
+}
+
 // One classical RK4 step with
 //   |dlam| = eps / (|K^r|/r + |K^theta| max(1, |cot theta|) + |K^phi|),
 // dlam < 0: relative change of r, change of theta and phi, and relative change
 // of sin(theta) bounded by eps, so steps shrink near the polar axis where the
-// coordinate frame turns quickly.  Returns dlam.
-KRT_HD double rk4_step(double a, double m, double eps, double y[7]) {
-    double sn, cs;
-    sincos(y[1], &sn, &cs);
+// coordinate frame turns quickly.  (sn, cs) hold sin and cos of theta at the
+// start point on entry and at the end point on return, so each point's sincos
+// serves the stop test after the step and the first stage of the next one.
+// The stage sum k1 + 2 k2 + 2 k3 + k4 is accumulated as the stages are made.
+// Returns dlam.
+KRT_HD double rk4_step(double a, double m, double eps, double y[7], double& sn, double& cs) {
+    double k[7], ks[7], yt[7];
+    geo_rhs_sc(a, m, y, sn, cs, k);
     const double h = -eps / (fabs(y[4]) / y[0] + fabs(y[5]) * fmax(1.0, fabs(cs / sn)) + fabs(y[6]));
-    double k1[7], k2[7], k3[7], k4[7], yt[7];
-    geo_rhs(a, m, y, k1);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) yt[i] = y[i] + 0.5 * h * k1[i];
-    geo_rhs(a, m, yt, k2);
+    for (int i = 0; i < 7; ++i) {
+        ks[i] = k[i];
+        yt[i] = y[i] + 0.5 * h * k[i];
+    }
+    geo_rhs(a, m, yt, k);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) yt[i] = y[i] + 0.5 * h * k2[i];
-    geo_rhs(a, m, yt, k3);
+    for (int i = 0; i < 7; ++i) {
+        ks[i] += 2.0 * k[i];
+        yt[i] = y[i] + 0.5 * h * k[i];
+    }
+    geo_rhs(a, m, yt, k);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) yt[i] = y[i] + h * k3[i];
-    geo_rhs(a, m, yt, k4);
+    for (int i = 0; i < 7; ++i) {
+        ks[i] += 2.0 * k[i];
+        yt[i] = y[i] + h * k[i];
+    }
+    geo_rhs(a, m, yt, k);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) y[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    for (int i = 0; i < 7; ++i) y[i] += h / 6.0 * (ks[i] + k[i]);
+    sincos(y[1], &sn, &cs);
     return h;
 }
 
 // Stop rule after step n, in order: non-finite, axis, capture, escape, cap.
-KRT_HD uint8_t stop_test(const TraceArgs& A, const double y[7], double h,
-                                             int n) {
+// sn = sin(theta) at the new point.
+KRT_HD uint8_t stop_test(const TraceArgs& A, const double y[7], double h, int n, double sn) {
     bool finite = is_finite(h);
 #pragma unroll
     for (int i = 0; i < 7; ++i) finite = finite && is_finite(y[i]);
     if (!finite) return kNonFinite;
-    if (sin(y[1]) < 1e-12) return kAxis;
+    if (sn < 1e-12) return kAxis;
     if (y[0] < A.r_stop) return kCaptured;
     if (y[0] > A.cam.r_cam && y[4] * h > 0.0) return kEscaped;
     if (n >= A.max_steps) return kStepCap;
@@ -114,6 +134,64 @@ KRT_HD void load_point(const double* p, double v[8]) {
     const double2 a = q[0], b = q[1], c = q[2], d = q[3];
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
     v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y;
+}
+
+// ---------------------------------------------------------------------------
+// Uniform FP64 parameters (spin, mass, camera, plasma model) are kernel
+// arguments in scalar registers, but FP64 arithmetic runs only on the vector
+// ALU, so every loop-invariant expression of them that the optimizer hoists out
+// of the persistent loops holds a vector register pair for the whole kernel.
+// Passing them through an empty asm inside the loop that uses them makes them
+// opaque there: the few derived values are recomputed where they are needed
+// and the registers go to the per-ray state instead.
+// ---------------------------------------------------------------------------
+KRT_HD double opaque(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(x));
+#endif
+    return x;
+}
+
+KRT_HD void launder_camera(CameraDesc& c) {
+    c.a = opaque(c.a);
+    c.m = opaque(c.m);
+    c.r_cam = opaque(c.r_cam);
+    c.th = opaque(c.th);
+    c.ph = opaque(c.ph);
+    c.fov_x = opaque(c.fov_x);
+    c.fov_y = opaque(c.fov_y);
+    c.freq = opaque(c.freq);
+}
+
+// The parameters read by the transfer at one point.
+KRT_HD void launder_transfer(TraceArgs& L) {
+    L.cam.a = opaque(L.cam.a);
+    L.cam.m = opaque(L.cam.m);
+    L.cam.freq = opaque(L.cam.freq);
+    L.fac0 = opaque(L.fac0);
+    if (L.model == kModelSnapshot) {
+        SnapDesc& q = L.snap;
+        q.x1s = opaque(q.x1s);
+        q.dx1 = opaque(q.dx1);
+        q.x2s = opaque(q.x2s);
+        q.dx2 = opaque(q.dx2);
+        q.x3s = opaque(q.x3s);
+        q.dx3 = opaque(q.dx3);
+        q.h = opaque(q.h);
+        q.gam = opaque(q.gam);
+        q.rho_unit = opaque(q.rho_unit);
+        q.B_unit = opaque(q.B_unit);
+        q.Rhigh = opaque(q.Rhigh);
+        q.Rlow = opaque(q.Rlow);
+        q.sigma_cut = opaque(q.sigma_cut);
+        q.rmax = opaque(q.rmax);
+    } else {
+        L.adaf.n0 = opaque(L.adaf.n0);
+        L.adaf.T0 = opaque(L.adaf.T0);
+        L.adaf.beta = opaque(L.adaf.beta);
+        L.adaf.h = opaque(L.adaf.h);
+        L.adaf.risco = opaque(L.adaf.risco);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -174,9 +252,8 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
             bn > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (bn * (-Ku))
                      : 0.0;
         double c[8];
-        thermal_coefficients(A.btab, p.ne, p.thetae, p.B, nu, cth, c);
-        const double fac = A.L_cm / A.cam.freq * nu;
-        const double seq = (c[3] > 0.0) ? source_function(p.thetae, nu) : 0.0;
+        const double seq = thermal_coefficients(A.btab, p.ne, p.thetae, p.B, nu, cth, c);
+        const double fac = A.fac0 * nu;
         double e1[4], l1[4], e2[4], l2[4];
         fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
         double S[4];
@@ -283,12 +360,16 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
             if (m <= n_end) {
                 double pt[8];
                 load_point(slot + ((size_t)m * 64 + lane) * 8, pt);
-                transfer_point(A, pt, m, m == n_end, xs, N);
+                TraceArgs L = A;
+                launder_transfer(L);
+                transfer_point(L, pt, m, m == n_end, xs, N);
             }
         }
         if (xfer) {
             double S[4];
-            camera_output(A, alpha, beta, N, S);
+            TraceArgs L = A;
+            launder_camera(L.cam);
+            camera_output(L, alpha, beta, N, S);
             write_pixel(A, pix, S, st, n);
         }
     }
@@ -298,8 +379,18 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
 // Persistent wave-synchronous tracer.  kGeoOnly: geodesic phase only, writing
 // the end state (no store, no transfer).
 // ---------------------------------------------------------------------------
+// Two waves per SIMD (at most 256 registers per lane): with one, the FP64
+// dependency chains of a single wave leave the vector ALU idle.
 template <bool kGeoOnly>
-__global__ __launch_bounds__(256) void trace_waves(TraceArgs A) {
+__global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
+    // The Bessel-ratio table (15 KiB) is read at every transfer point with
+    // lane-dependent panels: serve it from LDS.
+    __shared__ double s_btab[kBesPanels * 2 * kBesCoef];
+    if (!kGeoOnly) {
+        for (int k = threadIdx.x; k < kBesPanels * 2 * kBesCoef; k += blockDim.x) s_btab[k] = A.btab[k];
+        __syncthreads();
+        A.btab = s_btab;
+    }
     const int lane = threadIdx.x & 63;
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
@@ -318,12 +409,16 @@ __global__ __launch_bounds__(256) void trace_waves(TraceArgs A) {
         double alpha = 0.0, beta = 0.0;
         double y[7];
         {
-            pixel_position(A.cam, valid ? i : 0, valid ? j : 0, alpha, beta);
+            CameraDesc C = A.cam;
+            launder_camera(C);
+            pixel_position(C, valid ? i : 0, valid ? j : 0, alpha, beta);
             double X[4], K[4];
-            camera_launch(A.cam, alpha, beta, X, K);
+            camera_launch(C, alpha, beta, X, K);
             y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
             y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
         }
+        double sn, cs;
+        sincos(y[1], &sn, &cs);
         if (!kGeoOnly && valid) store_point(slot + (size_t)lane * 8, y, 0.0);
 
         // ---- backward geodesic, one step per lane per iteration ----
@@ -331,11 +426,11 @@ __global__ __launch_bounds__(256) void trace_waves(TraceArgs A) {
         int n = 0;
         double hlast = 0.0;
         while (st == kRunning) {
-            const double h = rk4_step(A.cam.a, A.cam.m, A.eps, y);
+            const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
             ++n;
             hlast = h;
             if (!kGeoOnly) store_point(slot + ((size_t)n * 64 + lane) * 8, y, h);
-            st = stop_test(A, y, h, n);
+            st = stop_test(A, y, h, n, sn);
             if (!kGeoOnly && st == kRunning && n >= A.cap - 1) st = kOverflow;
         }
 
@@ -365,21 +460,25 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         const int pix = A.overflow_list[k];
         const int i = pix % A.cam.nx, j = pix / A.cam.nx;
         double alpha, beta, y[7];
-        pixel_position(A.cam, i, j, alpha, beta);
+        CameraDesc C = A.cam;
+        launder_camera(C);
+        pixel_position(C, i, j, alpha, beta);
         {
             double X[4], K[4];
-            camera_launch(A.cam, alpha, beta, X, K);
+            camera_launch(C, alpha, beta, X, K);
             y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
             y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
         }
         store_point(path, y, 0.0);
+        double sn, cs;
+        sincos(y[1], &sn, &cs);
         uint8_t st = kRunning;
         int n = 0;
         while (st == kRunning) {
-            const double h = rk4_step(A.cam.a, A.cam.m, A.eps, y);
+            const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
             ++n;
             store_point(path + (size_t)n * 8, y, h);
-            st = stop_test(A, y, h, n);
+            st = stop_test(A, y, h, n, sn);
         }
         const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
         XferState xs;
@@ -387,10 +486,15 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         for (int m = n_end; m >= 0; --m) {
             double pt[8];
             load_point(path + (size_t)m * 8, pt);
-            transfer_point(A, pt, m, m == n_end, xs, N);
+            TraceArgs L = A;
+            launder_transfer(L);
+            transfer_point(L, pt, m, m == n_end, xs, N);
         }
         double S[4];
-        camera_output(A, alpha, beta, N, S);
+        launder_camera(C);
+        TraceArgs L = A;
+        L.cam = C;
+        camera_output(L, alpha, beta, N, S);
         write_pixel(A, pix, S, st, n);
         // the wave-synchronous pass counted this ray as overflow; count it now
         atomicAdd(&A.counters[0], (unsigned long long)n);

@@ -84,10 +84,14 @@ def pixel_sample(nx, ny, count, seed):
 # Synthetic GRMHD-like snapshot on a modified Kerr-Schild grid: a torus
 # profile with seeded power-law Gaussian random fluctuations (a stand-in for
 # the paper's GRMHD slice, which is not available).  Primitives (rho, u, U1,
-# U2, U3, B1, B2, B3) in code units, layout [n1][n2][n3][8].
+# U2, U3, B1, B2, B3) in code units, layout [n1][n2][n3][8].  The code-unit
+# density scale is set so that the mass unit 1e19 g puts the 230 GHz flux of
+# the 288 x 128 x 128 snapshot seen at 20 degrees at 2.4 Jy (Sgr A*-like, the
+# way GRMHD images are normalised); mass units 1e17 to 1e20 g then run from
+# optically thin to thick.
 # ---------------------------------------------------------------------------
 
-def snapshot_desc(n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=0.3, M_unit_g=10 ** 18.5,
+def snapshot_desc(n1=288, n2=128, n3=128, r_in=1.2, r_out=1000.0, hslope=0.3, M_unit_g=1e19,
                   R_high=40.0, R_low=1.0, sigma_cut=1.0, r_emit_max=50.0, gamma_ad=13.0 / 9.0):
     import math
     return {
@@ -138,4 +142,7 @@ def make_snapshot(desc, seed=7, a=0.94):
     btor = np.sqrt(2 * (desc["gamma_ad"] - 1) * uu / 10.0)
     P[..., 5] = 0.1 * np.sign(np.cos(th)) * (rh / r) ** 2 / r * (1 + 0.3 * d[4])
     P[..., 7] = btor / (r * np.maximum(np.sin(th), 1e-3)) * (1 + 0.3 * d[4])
+    # density scale 10^1.5 in code units: rho, u scale with it, B with its root
+    P[..., 0:2] *= 10 ** 1.5
+    P[..., 5:8] *= 10 ** 0.75
     return np.ascontiguousarray(P)
