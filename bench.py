@@ -26,11 +26,21 @@ if ROOT not in sys.path:
 # (bench.py --flop-probe, every lane tracing the same ray), 64 lanes per wave
 # instruction.  See the design doc (measurement).
 FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "4128.9"))
+# Same for the FP32-operator transfer (FP64 plus FP32 VALU operations; both run
+# at the same per-lane rate without packed FP32), None until measured.
+FLOPS_PER_RAY_STEP_F32 = None
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
+
+# HBM bytes per ray-step of trace_waves on the 1024^2 ADAF image: rocprofv3
+# FETCH_SIZE and WRITE_SIZE of one launch, each scaled by what the counter
+# reads for a copy of known size, divided by the launch's ray-steps (None
+# until measured on the current kernel).
+TRAFFIC_BYTES_PER_RAY_STEP = None
+TRAFFIC_WORKLOAD = "adaf1024"
 HBM_PEAK_GBS = 8000.0
 
 
-def run_probe(kind):
+def run_probe(kind, precision="fp64"):
     import torch
     from paper_2302_02733_amd import krt
     from paper_2302_02733_amd import workloads as W
@@ -45,6 +55,8 @@ def run_probe(kind):
         return
     cam = W.adaf_camera(256, jitter=0, fov=1e-9)
     with krt.Context(0) as ctx:
+        if precision == "fp32":
+            ctx.set_precision(krt.PRECISION_FP32_TRANSFER)
         ctx.set_units(W.UNITS)
         ctx.set_model(W.ADAF)
         out = ctx.trace(cam)
@@ -54,6 +66,9 @@ def run_probe(kind):
 
 
 def cpu_baseline(w, sample, snap_host=None):
+    """The oracle on the host cores over a seeded pixel sample, all threads,
+    then one thread on an eighth of the sample (the paper's CPU timings are
+    single-threaded)."""
     import numpy as np
     import oracle
     from paper_2302_02733_amd import workloads as W
@@ -64,20 +79,29 @@ def cpu_baseline(w, sample, snap_host=None):
     t0 = time.perf_counter()
     S, st, ns = oracle.render(cam, w["units"], w["model"], snap=snap, pixels=pix, threads=threads)
     dt = time.perf_counter() - t0
+    pix1 = pix[::8]
+    t0 = time.perf_counter()
+    oracle.render(cam, w["units"], w["model"], snap=snap, pixels=pix1, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": len(pix) / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(pix)} seeded pixels (seed 7) of the {cam['nx']}x{cam['ny']} image, "
-                      f"{int(np.sum(ns))} ray-steps, {dt:.1f} s wall"}
+                      f"{int(np.sum(ns))} ray-steps, {dt:.1f} s wall",
+            "single_thread": {"value": len(pix1) / dt1, "unit": "rays/s",
+                              "sample": f"every 8th pixel of that sample ({len(pix1)}), {dt1:.1f} s wall"}}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="adaf1024",
                     choices=["adaf64", "adaf1024", "adaf4096", "snap48", "snap2048"])
     ap.add_argument("--cpu-sample", type=int, default=4096, help="pixels for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="fp32: FP32 transfer operators with FP64 geodesics and FP64 transfer state "
+                         "(and the FP32 copy of the snapshot)")
     ap.add_argument("--flop-probe", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -86,9 +110,10 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.flop_probe or args.copy_probe:
-        run_probe("flop" if args.flop_probe else "copy")
+        run_probe("flop" if args.flop_probe else "copy", args.precision)
         return
 
+    import numpy as np
     import torch
     from paper_2302_02733_amd import krt
     from paper_2302_02733_amd import workloads as W
@@ -100,11 +125,20 @@ def main():
     stokes = torch.empty((4, cam["ny"], cam["nx"]), dtype=torch.float64, device=dev)
     status = torch.empty((cam["ny"], cam["nx"]), dtype=torch.uint8, device=dev)
     prims = snap_host = None
+    f32 = args.precision == "fp32"
     if "snapshot" in w:
         desc, seed = w["snapshot"]
         snap_host = W.make_snapshot(desc, seed)
-        prims = torch.tensor(snap_host, device=dev)
+        if f32:
+            # the FP32 copy; the oracle baseline reads the same values widened
+            snap_host = snap_host.astype(np.float32)
+            prims = torch.tensor(snap_host, device=dev)
+            snap_host = snap_host.astype(np.float64)
+        else:
+            prims = torch.tensor(snap_host, device=dev)
     with krt.Context(0) as ctx:
+        if f32:
+            ctx.set_precision(krt.PRECISION_FP32_TRANSFER)
         ctx.set_units(w["units"])
         if prims is not None:
             ctx.set_model_snapshot(w["snapshot"][0], prims)
@@ -130,28 +164,36 @@ def main():
 
     ms_per_step = 1e3 * dt / args.steps
     kernel_ms = sum(kms) / len(kms)
+    kernel_ms_median = sorted(kms)[len(kms) // 2]
     ray_steps = sum(steps) / len(steps)
-    if FLOPS_PER_RAY_STEP:
-        achieved = FLOPS_PER_RAY_STEP * ray_steps / (kernel_ms * 1e-3) / 1e12
+    fprs = FLOPS_PER_RAY_STEP_F32 if f32 else FLOPS_PER_RAY_STEP
+    if fprs:
+        achieved = fprs * ray_steps / (kernel_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                "kernel": "trace_waves", "kernel_ms": kernel_ms,
-                "flops_per_ray_step": FLOPS_PER_RAY_STEP}
+                "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": (TRAFFIC_BYTES_PER_RAY_STEP * ray_steps
+                            if TRAFFIC_BYTES_PER_RAY_STEP and args.workload == TRAFFIC_WORKLOAD and not f32
+                            else None),
+                "kernel": "trace_waves", "kernel_ms": kernel_ms, "kernel_ms_median": kernel_ms_median,
+                "flops_per_ray_step": fprs}
     else:
         roof = {"bound": "alu", "achieved": None, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": None, "traffic": None, "kernel": "trace_waves", "kernel_ms": kernel_ms}
     line = {
-        "metric": "polarized rays/s (FP64 geodesic + FP64 polarized transfer, whole image)",
+        "metric": ("polarized rays/s (FP64 geodesic + FP32-operator polarized transfer, whole image)" if f32
+                   else "polarized rays/s (FP64 geodesic + FP64 polarized transfer, whole image)"),
         "value": args.steps * npix / dt,
         "unit": "rays/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": "f64+f32" if f32 else "f64", "data": "synthetic",
         "config": {"workload": args.workload,
                    "model": ("analytic ADAF (a=0.9375, 60 deg, 230 GHz)" if prims is None else
                              "synthetic GRMHD-like snapshot 288x128x128 (a=0.94, 20 deg, 230 GHz)"),
                    "pixels": npix, "eps": cam["eps"], "max_steps": cam["max_steps"],
+                   "precision": ("FP64 geodesics, FP32 transfer operators, FP64 transfer state"
+                                 if f32 else "FP64 throughout"),
                    "parallelism": "single GPU"},
         "ray_steps_per_s": ray_steps / (ms_per_step * 1e-3),
         "mean_steps_per_ray": ray_steps / npix,

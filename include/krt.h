@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 1
+#define KRT_ABI_VERSION 2
 
 typedef enum {
     KRT_OK = 0,
@@ -163,11 +163,27 @@ krt_status krt_set_units(krt_ctx* ctx, const krt_units* units);
 /* Selects the analytic ADAF model with these parameters. */
 krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* adaf);
 
+/* Element types of snapshot primitives. */
+enum { KRT_DTYPE_F64 = 0, KRT_DTYPE_F32 = 1 };
+
 /* Selects the snapshot model.  d_prims (device memory, layout per desc,
- * dtype 0 = FP64) is borrowed until the model is replaced or the context is
- * destroyed; the caller must keep it alive and unchanged meanwhile. */
+ * element type KRT_DTYPE_F64 or KRT_DTYPE_F32: the FP32 copy halves the
+ * gather traffic and is read by both transfer precisions) is borrowed until
+ * the model is replaced or the context is destroyed; the caller must keep it
+ * alive and unchanged meanwhile.  Errors: KRT_E_INVAL, KRT_E_UNSUPPORTED
+ * (other dtype or layout). */
 krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc,
                                   const void* d_prims, int dtype);
+
+/* Arithmetic of the polarized transfer (Sec. 4 of the paper names single
+ * precision as the next speed-up).  KRT_PRECISION_FP64 (default): everything
+ * FP64.  KRT_PRECISION_FP32_TRANSFER: geodesics, their step control and the
+ * stored path stay FP64; the operators of each transfer step (metric and
+ * connection, plasma, coefficients, fluid tetrad, propagator) are FP32, while
+ * the coherency matrix and the transport state stay FP64 and every increment
+ * is added in FP64.  Applies to later krt_trace calls.  Errors: KRT_E_INVAL. */
+enum { KRT_PRECISION_FP64 = 0, KRT_PRECISION_FP32_TRANSFER = 1 };
+krt_status krt_set_precision(krt_ctx* ctx, int precision);
 
 /* ---- the hot path ---- */
 

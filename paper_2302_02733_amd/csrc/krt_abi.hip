@@ -24,12 +24,15 @@ struct krt_ctx {
     krt_adaf adaf{};
     krt_snapshot_desc snap{};
     const double* snap_prims = nullptr;
+    const float* snap_prims_f = nullptr;
+    int precision = KRT_PRECISION_FP64;
     double* btab = nullptr;
     // wave-synchronous path store
     double* pool = nullptr;
     size_t pool_bytes = 0;
     int pool_cap = 0;
-    int pool_blocks = 0;
+    int pool_blocks = 0;       // blocks the store holds slices for
+    int launch_blocks = 0;     // blocks of the current mode's launch (<= pool_blocks)
     // long-ray store
     double* long_pool = nullptr;
     size_t long_bytes = 0;
@@ -137,6 +140,7 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
         const krt_snapshot_desc& d = ctx->snap;
         const double L = A.L_cm;
         A.snap.prims = ctx->snap_prims;
+        A.snap.prims_f = ctx->snap_prims_f;
         A.snap.n1 = d.n1;
         A.snap.n2 = d.n2;
         A.snap.n3 = d.n3;
@@ -161,6 +165,41 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     A.adaf.h = ctx->adaf.h_over_r;
     A.adaf.risco = isco(cam->a);
     A.btab = ctx->btab;
+    {
+        // constants of the FP32 transfer operators, folded in FP64
+        F32Consts& C = A.f32;
+        const double nu = cam->freq_hz, L = A.L_cm, e2 = kE * kE;
+        C.a = (float)cam->a;
+        C.m = (float)A.cam.m;
+        C.cJ = (float)(e2 * nu / (2.0 * std::sqrt(3.0) * kC));
+        C.cRV = (float)(2.0 * e2 / (kME * kC * nu * nu));
+        C.cRQ = (float)(e2 / (kME * kC * nu * nu * nu));
+        C.cHnu = (float)(kH * nu / (kME * kC * kC));
+        C.cBnu = (float)(2.0 * kH * nu * nu * nu / (kC * kC));
+        C.cSeq = (float)(kIScale * 2.0 * kH / (kC * kC));
+        C.nu_cam = (float)nu;
+        C.L = (float)L;
+        C.n0 = (float)A.adaf.n0;
+        C.thr = (float)(kKB * A.adaf.T0 / (kME * kC * kC));
+        C.cB2 = (float)(A.adaf.beta > 0.0 ? 8.0 * kPi * kMP * kC * kC / (6.0 * A.adaf.beta) : 0.0);
+        C.ih2 = (float)(A.adaf.h > 0.0 ? 1.0 / (2.0 * A.adaf.h * A.adaf.h) : 0.0);
+        C.risco = (float)A.adaf.risco;
+        if (ctx->model == kModelSnapshot) {
+            C.x1s = (float)A.snap.x1s;
+            C.idx1 = (float)(1.0 / A.snap.dx1);
+            C.x2s = (float)A.snap.x2s;
+            C.idx2 = (float)(1.0 / A.snap.dx2);
+            C.hh = (float)(0.5 * (1.0 - A.snap.h));
+            C.gm1 = (float)(A.snap.gam - 1.0);
+            C.ne_unit = (float)(A.snap.rho_unit / (kMP + kME));
+            C.B_unit = (float)A.snap.B_unit;
+            C.Rhigh = (float)A.snap.Rhigh;
+            C.Rlow = (float)A.snap.Rlow;
+            C.sigma_cut = (float)A.snap.sigma_cut;
+            C.rmax = (float)A.snap.rmax;
+            C.mpme = (float)(kMP / kME);
+        }
+    }
     A.tiles_x = (cam->nx + 7) / 8;
     A.nbatch = A.tiles_x * ((cam->ny + 7) / 8);
     A.queue = ctx->work;
@@ -170,20 +209,26 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
 }
 
 // Sizes the wave-synchronous store: one slice of `cap` points for every
-// wavefront of the persistent grid (as many blocks as fit on the device).
+// wavefront of the persistent grid of the kernel about to run (as many blocks
+// as fit on the device, within the KRT_POOL_GB budget).  The store only grows.
+template <int kMode>
 krt_status ensure_pool(krt_ctx* ctx) {
     const int cap = env_int("KRT_PATH_CAP", 8192);
-    const double budget_gb = (double)env_int("KRT_POOL_GB", 64);
+    const double budget_gb = (double)env_int("KRT_POOL_GB", 96);
     int per_cu = 0;
-    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<false>, 256, 0));
+    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<kMode>, 256, 0));
     if (per_cu < 1) per_cu = 1;
     int blocks = per_cu * ctx->cu_count;
     const size_t per_block = (size_t)4 * 64 * cap * 8 * sizeof(double);
     const size_t budget = (size_t)(budget_gb * 1073741824.0);
     if ((size_t)blocks * per_block > budget) blocks = (int)(budget / per_block);
     if (blocks < 1) return fail(ctx, KRT_E_NOMEM, "path store budget too small");
+    ctx->launch_blocks = blocks;
+    if (ctx->pool && ctx->pool_cap == cap && ctx->pool_blocks >= blocks) {
+        ctx->launch_blocks = blocks;
+        return KRT_OK;
+    }
     const size_t need = (size_t)blocks * per_block;
-    if (ctx->pool && ctx->pool_cap == cap && ctx->pool_blocks == blocks) return KRT_OK;
     if (ctx->pool) {
         KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
         KRT_HIP(ctx, hipFree(ctx->pool));
@@ -197,6 +242,7 @@ krt_status ensure_pool(krt_ctx* ctx) {
     ctx->pool_bytes = need;
     ctx->pool_cap = cap;
     ctx->pool_blocks = blocks;
+    ctx->launch_blocks = blocks;
     return KRT_OK;
 }
 
@@ -380,7 +426,8 @@ krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, c
     if (!ctx) return KRT_E_INVAL;
     if (!desc || desc->struct_size != sizeof(krt_snapshot_desc)) return fail(ctx, KRT_E_INVAL, "bad snapshot struct");
     if (!d_prims) return fail(ctx, KRT_E_INVAL, "d_prims is NULL");
-    if (dtype != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only FP64 primitives (dtype 0) are supported");
+    if (dtype != KRT_DTYPE_F64 && dtype != KRT_DTYPE_F32)
+        return fail(ctx, KRT_E_UNSUPPORTED, "dtype must be KRT_DTYPE_F64 or KRT_DTYPE_F32");
     if (desc->layout != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only layout 0 is supported");
     const krt_snapshot_desc& d = *desc;
     if (d.n1 < 2 || d.n2 < 2 || d.n3 < 1) return fail(ctx, KRT_E_INVAL, "grid needs n1, n2 >= 2 and n3 >= 1");
@@ -392,8 +439,17 @@ krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, c
     if (!(d.M_unit_g > 0.0) || !(d.gamma_ad > 1.0)) return fail(ctx, KRT_E_INVAL, "need M_unit > 0, gamma_ad > 1");
     if (!(d.hslope > 0.0 && d.hslope <= 1.0)) return fail(ctx, KRT_E_INVAL, "hslope must be in (0, 1]");
     ctx->snap = d;
-    ctx->snap_prims = static_cast<const double*>(d_prims);
+    ctx->snap_prims = dtype == KRT_DTYPE_F64 ? static_cast<const double*>(d_prims) : nullptr;
+    ctx->snap_prims_f = dtype == KRT_DTYPE_F32 ? static_cast<const float*>(d_prims) : nullptr;
     ctx->model = kModelSnapshot;
+    return KRT_OK;
+}
+
+krt_status krt_set_precision(krt_ctx* ctx, int precision) {
+    if (!ctx) return KRT_E_INVAL;
+    if (precision != KRT_PRECISION_FP64 && precision != KRT_PRECISION_FP32_TRANSFER)
+        return fail(ctx, KRT_E_INVAL, "precision must be KRT_PRECISION_FP64 or KRT_PRECISION_FP32_TRANSFER");
+    ctx->precision = precision;
     return KRT_OK;
 }
 
@@ -404,7 +460,8 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     if (!d_stokes) return fail(ctx, KRT_E_INVAL, "d_stokes is NULL");
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     const size_t npix = (size_t)cam->nx * cam->ny;
-    if ((st = ensure_pool(ctx)) != KRT_OK) return st;
+    const bool f32 = ctx->precision == KRT_PRECISION_FP32_TRANSFER;
+    if ((st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx)) != KRT_OK) return st;
     if ((st = ensure_long(ctx, cam->max_steps, npix)) != KRT_OK) return st;
     TraceArgs A = base_args(ctx, cam);
     A.pool = ctx->pool;
@@ -417,10 +474,16 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     A.nsteps = d_nsteps;
     KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    hipLaunchKernelGGL(trace_waves<false>, dim3(ctx->pool_blocks), dim3(256), 0, ctx->stream, A);
+    if (f32)
+        hipLaunchKernelGGL(trace_waves<kModeF32>, dim3(ctx->launch_blocks), dim3(256), 0, ctx->stream, A);
+    else
+        hipLaunchKernelGGL(trace_waves<kModeF64>, dim3(ctx->launch_blocks), dim3(256), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
-    hipLaunchKernelGGL(trace_long, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+    if (f32)
+        hipLaunchKernelGGL(trace_long<kModeF32>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+    else
+        hipLaunchKernelGGL(trace_long<kModeF64>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
     if (out_stats) return fill_stats(ctx, cam, out_stats);
@@ -444,10 +507,10 @@ krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_
     A.nsteps = d_nsteps;
     A.status = d_status;
     int per_cu = 0;
-    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<true>, 256, 0));
+    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<kModeGeo>, 256, 0));
     const int blocks = (per_cu < 1 ? 1 : per_cu) * ctx->cu_count;
     KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
-    hipLaunchKernelGGL(trace_waves<true>, dim3(blocks), dim3(256), 0, ctx->stream, A);
+    hipLaunchKernelGGL(trace_waves<kModeGeo>, dim3(blocks), dim3(256), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     return KRT_OK;
 }

@@ -357,7 +357,8 @@ KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const 
 // theta = pi x2 + (1 - h)/2 sin(2 pi x2), x3 = phi; cell-centred primitives
 // (rho, u, U1, U2, U3, B1, B2, B3), layout [n1][n2][n3][8].
 struct SnapDesc {
-    const double* prims;
+    const double* prims;       // FP64 primitives, or null when prims_f is set
+    const float* prims_f;      // FP32 primitives (same layout)
     int n1, n2, n3;
     double x1s, dx1, x2s, dx2, x3s, dx3;
     double h, gam;
@@ -400,11 +401,18 @@ KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, 
         const int ic = (c & 1) ? i1[2] : i0[2];
         const double w = ((c & 4) ? d[0] : 1.0 - d[0]) * ((c & 2) ? d[1] : 1.0 - d[1]) *
                          ((c & 1) ? d[2] : 1.0 - d[2]);
-        const double2* cell =
-            reinterpret_cast<const double2*>(s.prims + 8 * (((size_t)ia * s.n2 + ib) * s.n3 + ic));
-        const double2 v0 = cell[0], v1 = cell[1], v2 = cell[2], v3 = cell[3];
-        P[0] += w * v0.x; P[1] += w * v0.y; P[2] += w * v1.x; P[3] += w * v1.y;
-        P[4] += w * v2.x; P[5] += w * v2.y; P[6] += w * v3.x; P[7] += w * v3.y;
+        const size_t off = 8 * (((size_t)ia * s.n2 + ib) * s.n3 + ic);
+        if (s.prims_f) {
+            const float4* cell = reinterpret_cast<const float4*>(s.prims_f + off);
+            const float4 v0 = cell[0], v1 = cell[1];
+            P[0] += w * v0.x; P[1] += w * v0.y; P[2] += w * v0.z; P[3] += w * v0.w;
+            P[4] += w * v1.x; P[5] += w * v1.y; P[6] += w * v1.z; P[7] += w * v1.w;
+        } else {
+            const double2* cell = reinterpret_cast<const double2*>(s.prims + off);
+            const double2 v0 = cell[0], v1 = cell[1], v2 = cell[2], v3 = cell[3];
+            P[0] += w * v0.x; P[1] += w * v0.y; P[2] += w * v1.x; P[3] += w * v1.y;
+            P[4] += w * v2.x; P[5] += w * v2.y; P[6] += w * v3.x; P[7] += w * v3.y;
+        }
     }
 }
 

@@ -12,6 +12,7 @@
 #pragma once
 
 #include "krt_device.hpp"
+#include "krt_f32.hpp"
 
 namespace krt {
 
@@ -19,6 +20,9 @@ enum : uint8_t { kEscaped = 0, kCaptured = 1, kStepCap = 2, kNonFinite = 3, kAxi
                  kRunning = 254, kOverflow = 255 };
 
 enum : int { kModelAdaf = 0, kModelSnapshot = 1 };
+
+// Kernel modes: FP64 transfer, geodesics only, FP32 transfer operators.
+enum : int { kModeF64 = 0, kModeGeo = 1, kModeF32 = 2 };
 
 struct TraceArgs {
     CameraDesc cam;
@@ -29,6 +33,8 @@ struct TraceArgs {
     AdafDesc adaf;
     SnapDesc snap;
     const double* btab;
+    const float* btab_f;   // FP32 copy of the table (set inside the kernel)
+    F32Consts f32;
     // path store of the wave-synchronous kernel
     double* pool;
     int cap;            // stored points per lane slice
@@ -281,6 +287,99 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
     }
 }
 
+// Mixed-precision version of transfer_point: the operators at the point in
+// FP32, the coherency matrix and the Heun state in FP64, every increment
+// formed in FP32 (scaled by 2^160) and added in FP64.  The radiative update
+// adds the coherency matrix of the Stokes increment on the fluid legs.
+KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bool first,
+                               XferState& st, Coh& N) {
+    const F32Consts& C = A.f32;
+    // sin and cos of theta from an argument reduced in FP64 toward the nearer pole
+    const double thd = pt[1];
+    const bool south = thd > 0.5 * kPi;
+    float s, c;
+    sincosf((float)(south ? kPi - thd : thd), &s, &c);
+    if (south) c = -c;
+    const float r = (float)pt[0];
+    const float K[4] = {(float)pt[3], (float)pt[4], (float)pt[5], (float)pt[6]};
+    const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
+    MetricF g;
+    MetricDF dr, dh;
+    metric_d_f(C.a, C.m, r, s, c, g, dr, dh);
+    float Ac[16];
+    connection_f(g, dr, dh, K, Ac);
+    double Dnext = 0.0;
+    if (first) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+    } else {
+        Dnext = st.Dnext;
+        CohF Nf, F;
+        to_scaled_f(st.Ns, Nf);
+        transport_rhs_f(Ac, Nf, F);
+        const double hh = 0.5 * Dnext * kIScaleInv;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) N.R[k] = st.H.R[k] + hh * (double)F.R[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) N.I[k] = st.H.I[k] + hh * (double)F.I[k];
+    }
+
+    PlasmaF p;
+    bool ok;
+    if (A.model == kModelSnapshot) {
+        const SnapDesc& q = A.snap;
+        double X2 = (pt[2] - q.x3s) / q.dx3 - 0.5;
+        X2 -= q.n3 * floor(X2 / q.n3);
+        ok = q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
+                       : snapshot_plasma_f(C, q.prims, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p);
+    } else {
+        ok = adaf_plasma_f(C, r, g, p);
+    }
+    if (ok) {
+        float Kl[4];
+        lower_f(g, K, Kl);
+        const float Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
+        const float gz = -Ku;  // nu / nu_cam
+        const float bb = dot_f(g, p.b, p.b);
+        const float bn = bb > 0.0f ? sqrtf(bb) : 0.0f;
+        const float cth =
+            bn > 0.0f ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (bn * gz)
+                      : 0.0f;
+        float co[5];
+        const float seq = thermal_f(C, A.btab_f, p.ne, p.thetae, p.B, gz, cth, co);
+        // invariant coefficients (x L nu / nu_cam) times the step length
+        const float w = (float)(0.5 * (Dn + Dnext)) * C.L * gz;
+        float e1[4], l1[4], e2[4], l2[4];
+        fluid_legs_f(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+        CohF Nf;
+        to_scaled_f(N, Nf);
+        float S[4], dS[4];
+        coh_project_f(Nf, l1, l2, S);
+        mueller_delta_f(seq, co[0] * w, co[1] * w, co[2] * w, co[3] * w, co[4] * w, S, dS);
+        coh_add_delta_f(N, dS, e1, e2);
+    }
+
+    if (n > 0) {
+        CohF Nf, F;
+        to_scaled_f(N, Nf);
+        transport_rhs_f(Ac, Nf, F);
+        const double hh = 0.5 * Dn * kIScaleInv, hf = Dn * kIScaleInv;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            st.H.R[k] = N.R[k] + hh * (double)F.R[k];
+            st.Ns.R[k] = N.R[k] + hf * (double)F.R[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            st.H.I[k] = N.I[k] + hh * (double)F.I[k];
+            st.Ns.I[k] = N.I[k] + hf * (double)F.I[k];
+        }
+        st.Dnext = Dn;
+    }
+}
+
 // Camera output: project N on the pixel's screen legs, times nu_obs^3.
 KRT_HD void camera_output(const TraceArgs& A, double alpha, double beta,
                                               const Coh& N, double S[4]) {
@@ -331,6 +430,7 @@ __device__ __forceinline__ void account(const TraceArgs& A, bool valid, uint8_t 
 
 // Transfer phase of one 8x8 tile (all lanes on the same point index, far
 // end first), output and accounting.
+template <int kMode>
 __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot, int lane,
                                                bool valid, int pix, double alpha, double beta,
                                                uint8_t st, int n) {
@@ -362,7 +462,10 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
                 load_point(slot + ((size_t)m * 64 + lane) * 8, pt);
                 TraceArgs L = A;
                 launder_transfer(L);
-                transfer_point(L, pt, m, m == n_end, xs, N);
+                if (kMode == kModeF32)
+                    transfer_point_f32(L, pt, m, m == n_end, xs, N);
+                else
+                    transfer_point(L, pt, m, m == n_end, xs, N);
             }
         }
         if (xfer) {
@@ -376,20 +479,28 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
 }
 
 // ---------------------------------------------------------------------------
-// Persistent wave-synchronous tracer.  kGeoOnly: geodesic phase only, writing
+// Persistent wave-synchronous tracer.  kMode: FP64 transfer, FP32 transfer
+// operators, or (kModeGeo) the geodesic phase only, writing
 // the end state (no store, no transfer).
 // ---------------------------------------------------------------------------
 // Two waves per SIMD (at most 256 registers per lane): with one, the FP64
 // dependency chains of a single wave leave the vector ALU idle.
-template <bool kGeoOnly>
+template <int kMode>
 __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
-    // The Bessel-ratio table (15 KiB) is read at every transfer point with
-    // lane-dependent panels: serve it from LDS.
-    __shared__ double s_btab[kBesPanels * 2 * kBesCoef];
-    if (!kGeoOnly) {
-        for (int k = threadIdx.x; k < kBesPanels * 2 * kBesCoef; k += blockDim.x) s_btab[k] = A.btab[k];
+    constexpr bool kGeoOnly = kMode == kModeGeo;
+    // The Bessel-ratio table (15 KiB in FP64, 7.5 KiB in FP32) is read at
+    // every transfer point with lane-dependent panels: serve it from LDS.
+    constexpr int kTab = kBesPanels * 2 * kBesCoef;
+    __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
+    __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
+    if (kMode == kModeF64) {
+        for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_btab[k] = A.btab[k];
         __syncthreads();
         A.btab = s_btab;
+    } else if (kMode == kModeF32) {
+        for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_btab_f[k] = (float)A.btab[k];
+        __syncthreads();
+        A.btab_f = s_btab_f;
     }
     const int lane = threadIdx.x & 63;
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -444,14 +555,22 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
             }
             account(A, valid, st, n);
         } else {
-            trace_transfer(A, slot, lane, valid, pix, alpha, beta, st, n);
+            trace_transfer<kMode>(A, slot, lane, valid, pix, alpha, beta, st, n);
         }
     }
 }
 
 // Rays longer than the wave-synchronous store: one ray per lane with a
 // full-length private store ([point][8]); lanes loop over the overflow list.
+template <int kMode>
 __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
+    __shared__ float s_btab_f[kMode == kModeF32 ? kBesPanels * 2 * kBesCoef : 1];
+    if (kMode == kModeF32) {
+        for (int k = threadIdx.x; k < kBesPanels * 2 * kBesCoef; k += blockDim.x)
+            s_btab_f[k] = (float)A.btab[k];
+        __syncthreads();
+        A.btab_f = s_btab_f;
+    }
     const unsigned total = *A.overflow_count;
     const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned stride = gridDim.x * blockDim.x;
@@ -488,7 +607,10 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
             load_point(path + (size_t)m * 8, pt);
             TraceArgs L = A;
             launder_transfer(L);
-            transfer_point(L, pt, m, m == n_end, xs, N);
+            if (kMode == kModeF32)
+                transfer_point_f32(L, pt, m, m == n_end, xs, N);
+            else
+                transfer_point(L, pt, m, m == n_end, xs, N);
         }
         double S[4];
         launder_camera(C);

@@ -88,7 +88,13 @@ _SIGS = {
     "krt_coeffs": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "krt_bessel_ratios": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "krt_mueller_step": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_double, _P]),
+    "krt_set_precision": (ctypes.c_int, [_P, ctypes.c_int]),
 }
+
+PRECISION_FP64 = 0
+PRECISION_FP32_TRANSFER = 1
+DTYPE_F64 = 0
+DTYPE_F32 = 1
 
 _lib = None
 
@@ -182,17 +188,25 @@ class Context:
         self._check(lib().krt_set_model_adaf(self.h, ctypes.byref(m)))
 
     def set_model_snapshot(self, desc, prims):
-        """desc: snapshot description dict; prims: float64 [n1][n2][n3][8] device
-        tensor, borrowed (keep it alive while the model is in use)."""
+        """desc: snapshot description dict; prims: float64 or float32
+        [n1][n2][n3][8] device tensor, borrowed (keep it alive while the model
+        is in use)."""
         _dev(prims, self.device)
-        if prims.dtype != torch.float64 or tuple(prims.shape) != (desc["n1"], desc["n2"], desc["n3"], 8):
-            raise ValueError("prims must be float64 [n1][n2][n3][8]")
+        if prims.dtype not in (torch.float64, torch.float32) or \
+                tuple(prims.shape) != (desc["n1"], desc["n2"], desc["n3"], 8):
+            raise ValueError("prims must be float64 or float32 [n1][n2][n3][8]")
         d = SnapshotDesc()
         d.struct_size = ctypes.sizeof(SnapshotDesc)
         for name, _ in SnapshotDesc._fields_[1:]:
             setattr(d, name, desc.get(name, 0))
         self._snapshot = prims
-        self._check(lib().krt_set_model_snapshot(self.h, ctypes.byref(d), _ptr(prims), 0))
+        dtype = DTYPE_F64 if prims.dtype == torch.float64 else DTYPE_F32
+        self._check(lib().krt_set_model_snapshot(self.h, ctypes.byref(d), _ptr(prims), dtype))
+
+    def set_precision(self, precision):
+        """PRECISION_FP64 or PRECISION_FP32_TRANSFER (FP32 transfer operators,
+        FP64 geodesics and FP64 transfer state)."""
+        self._check(lib().krt_set_precision(self.h, int(precision)))
 
     def set_model(self, d, prims=None):
         kind = int(d.get("kind", 0))
