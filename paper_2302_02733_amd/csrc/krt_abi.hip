@@ -33,6 +33,11 @@ struct krt_ctx {
     int pool_cap = 0;
     int pool_blocks = 0;       // blocks the store holds slices for
     int launch_blocks = 0;     // blocks of the current mode's launch (<= pool_blocks)
+    // paged extension of the wave store
+    double* chunk_pool = nullptr;
+    unsigned* chunk_flags = nullptr;
+    int nchunks = 0;
+    int chunk_cap = 0;
     // long-ray store
     double* long_pool = nullptr;
     size_t long_bytes = 0;
@@ -246,6 +251,35 @@ krt_status ensure_pool(krt_ctx* ctx) {
     return KRT_OK;
 }
 
+// Chunks of the paged path store (KRT_CHUNKS, default 64, of cap x 64 lanes
+// x 64 B: 2 GiB at cap 8192), lent to waves whose rays outgrow their slice.
+krt_status ensure_chunks(krt_ctx* ctx) {
+    const int cap = ctx->pool_cap;
+    int count = env_int("KRT_CHUNKS", 64);
+    if (count < 0) count = 0;
+    if (count > 4096) count = 4096;
+    if (ctx->chunk_cap == cap && ctx->nchunks == count && (count == 0 || ctx->chunk_pool)) return KRT_OK;
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->chunk_pool) KRT_HIP(ctx, hipFree(ctx->chunk_pool));
+    if (ctx->chunk_flags) KRT_HIP(ctx, hipFree(ctx->chunk_flags));
+    ctx->chunk_pool = nullptr;
+    ctx->chunk_flags = nullptr;
+    ctx->nchunks = 0;
+    ctx->chunk_cap = cap;
+    if (count == 0) return KRT_OK;
+    const size_t bytes = (size_t)count * cap * 512 * sizeof(double);
+    if (hipMalloc(&ctx->chunk_pool, bytes) != hipSuccess ||
+        hipMalloc(&ctx->chunk_flags, (size_t)count * sizeof(unsigned)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->chunk_pool) (void)hipFree(ctx->chunk_pool);
+        ctx->chunk_pool = nullptr;
+        ctx->chunk_flags = nullptr;
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate the path chunks");
+    }
+    ctx->nchunks = count;
+    return KRT_OK;
+}
+
 krt_status ensure_long(krt_ctx* ctx, int max_steps, size_t npix) {
     if (ctx->long_pool == nullptr || ctx->long_max_steps != max_steps) {
         if (ctx->long_pool) {
@@ -384,6 +418,8 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->long_pool) (void)hipFree(ctx->long_pool);
     if (ctx->overflow_list) (void)hipFree(ctx->overflow_list);
     if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->chunk_pool) (void)hipFree(ctx->chunk_pool);
+    if (ctx->chunk_flags) (void)hipFree(ctx->chunk_flags);
     if (ctx->red_partial) (void)hipFree(ctx->red_partial);
     if (ctx->btab) (void)hipFree(ctx->btab);
     if (ctx->host_buf) (void)hipHostFree(ctx->host_buf);
@@ -462,10 +498,16 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     const size_t npix = (size_t)cam->nx * cam->ny;
     const bool f32 = ctx->precision == KRT_PRECISION_FP32_TRANSFER;
     if ((st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx)) != KRT_OK) return st;
+    if ((st = ensure_chunks(ctx)) != KRT_OK) return st;
     if ((st = ensure_long(ctx, cam->max_steps, npix)) != KRT_OK) return st;
     TraceArgs A = base_args(ctx, cam);
     A.pool = ctx->pool;
     A.cap = ctx->pool_cap;
+    A.chunk_pool = ctx->chunk_pool;
+    A.chunk_flags = ctx->chunk_flags;
+    A.nchunks = ctx->nchunks;
+    if (ctx->nchunks > 0)
+        KRT_HIP(ctx, hipMemsetAsync(ctx->chunk_flags, 0, (size_t)ctx->nchunks * sizeof(unsigned), ctx->stream));
     A.long_pool = ctx->long_pool;
     A.long_slots = ctx->long_slots;
     A.overflow_list = ctx->overflow_list;

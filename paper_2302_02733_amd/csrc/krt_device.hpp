@@ -428,10 +428,14 @@ KRT_HD bool snapshot_plasma(const SnapDesc& s, double a, double m, double r, dou
     const double x1 = log(r);
     double x2 = th * (1.0 / kPi);
     const double hh = 0.5 * (1.0 - s.h);
+    // Newton from theta/pi: quadratic convergence, at most 8 steps, stopping
+    // once a step no longer moves x2 beyond round-off
     for (int it = 0; it < 8; ++it) {
         double sn, cs;
         sincos(2.0 * kPi * x2, &sn, &cs);
-        x2 -= (kPi * x2 + hh * sn - th) / (kPi * (1.0 + (1.0 - s.h) * cs));
+        const double dx = (kPi * x2 + hh * sn - th) / (kPi * (1.0 + (1.0 - s.h) * cs));
+        x2 -= dx;
+        if (fabs(dx) < 1e-15) break;
     }
     double P[8];
     snapshot_interp(s, x1, x2, ph, P);

@@ -233,10 +233,12 @@ KRT_HD bool snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2
     const float kPif = 3.14159265f;
     float x2 = th * (1.0f / kPif);
     float cs2 = 1.0f;
-    for (int it = 0; it < 5; ++it) {
+    for (int it = 0; it < 8; ++it) {
         float sn;
         sincosf(2.0f * kPif * x2, &sn, &cs2);
-        x2 -= (kPif * x2 + C.hh * sn - th) / (kPif * (1.0f + 2.0f * C.hh * cs2));
+        const float dx = (kPif * x2 + C.hh * sn - th) / (kPif * (1.0f + 2.0f * C.hh * cs2));
+        x2 -= dx;
+        if (fabsf(dx) < 1e-7f) break;
     }
     cs2 = cosf(2.0f * kPif * x2);
     float Pv[8];

@@ -40,6 +40,11 @@ struct TraceArgs {
     int cap;            // stored points per lane slice
     int tiles_x, nbatch;
     unsigned* queue;    // [0]: next 8x8 tile
+    // paged extension of the wave store: chunks of `cap` points x 64 lanes,
+    // taken by a wave whose rays outgrow its slice, returned after the tile
+    double* chunk_pool;
+    unsigned* chunk_flags;  // [nchunks], 0 = free
+    int nchunks;
     // long rays
     double* long_pool;
     int long_slots;
@@ -428,10 +433,45 @@ __device__ __forceinline__ void account(const TraceArgs& A, bool valid, uint8_t 
     }
 }
 
+// Chunks of the paged path store one wave may hold for one tile: with the
+// default 8192-point slice, 6 chunks cover the 50 000-step cap.
+constexpr int kMaxChunks = 6;
+
+// Called together by the active lanes of a wave (all at the same point index)
+// whose slice is full: the first active lane takes a free chunk and records
+// it in the wave's LDS list at position k; returns its index (-1: none free).
+__device__ __forceinline__ int take_chunk(const TraceArgs& A, int* wchunks, int k, unsigned hint) {
+    const unsigned long long act = __ballot(1);
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    int id = -1;
+    if ((int)(threadIdx.x & 63) == leader) {
+        for (int t = 0; t < A.nchunks; ++t) {
+            const int c = (int)((hint + (unsigned)t) % (unsigned)A.nchunks);
+            if (atomicCAS(&A.chunk_flags[c], 0u, 1u) == 0u) {
+                id = c;
+                break;
+            }
+        }
+        if (id >= 0) wchunks[k] = id;
+    }
+    return __builtin_amdgcn_readfirstlane(id);
+}
+
+// Address of stored point m of this lane: the wave's slice for m < cap, then
+// the wave's chunks in the order taken.
+__device__ __forceinline__ const double* point_addr(const TraceArgs& A, const double* slot,
+                                                   const int* wchunks, int m, int lane) {
+    if (m < A.cap) return slot + ((size_t)m * 64 + lane) * 8;
+    const int k = m / A.cap - 1;
+    const int c = wchunks[k];
+    return A.chunk_pool + (size_t)c * A.cap * 512 + ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * 8;
+}
+
 // Transfer phase of one 8x8 tile (all lanes on the same point index, far
 // end first), output and accounting.
 template <int kMode>
-__device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot, int lane,
+__device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot, const int* wchunks,
+                                               int lane,
                                                bool valid, int pix, double alpha, double beta,
                                                uint8_t st, int n) {
     {
@@ -459,7 +499,7 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
         for (int m = nmax; m >= 0; --m) {
             if (m <= n_end) {
                 double pt[8];
-                load_point(slot + ((size_t)m * 64 + lane) * 8, pt);
+                load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 TraceArgs L = A;
                 launder_transfer(L);
                 if (kMode == kModeF32)
@@ -505,6 +545,8 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
     const int lane = threadIdx.x & 63;
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
+    __shared__ int s_chunks[4][kMaxChunks];
+    int* wchunks = s_chunks[threadIdx.x >> 6];
     for (;;) {
         // One queue ticket per wave, taken without a lane-divergent branch:
         // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
@@ -536,14 +578,39 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
         uint8_t st = valid ? kRunning : kEscaped;
         int n = 0;
         double hlast = 0.0;
+        // store of points [cstart, cstart + cap): the slice, then chunks; the
+        // lanes still stepping all sit at the same n, so nch, cstart and cbase
+        // agree among them
+        int nch = 0, cstart = 0;
+        double* cbase = slot;
         while (st == kRunning) {
             const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
             ++n;
             hlast = h;
-            if (!kGeoOnly) store_point(slot + ((size_t)n * 64 + lane) * 8, y, h);
+            if (!kGeoOnly) {
+                if (n == cstart + A.cap) {
+                    const int id = (nch < kMaxChunks && A.nchunks > 0)
+                                       ? take_chunk(A, wchunks, nch, (unsigned)wave * 7u + (unsigned)nch)
+                                       : -1;
+                    if (id < 0) {  // no chunk: the long-ray kernel redoes these rays
+                        st = kOverflow;
+                        continue;
+                    }
+                    ++nch;
+                    cstart += A.cap;
+                    cbase = A.chunk_pool + (size_t)id * A.cap * 512;
+                }
+                store_point(cbase + ((size_t)(n - cstart) * 64 + lane) * 8, y, h);
+            }
             st = stop_test(A, y, h, n, sn);
-            if (!kGeoOnly && st == kRunning && n >= A.cap - 1) st = kOverflow;
         }
+        // chunks this wave holds for the tile
+        int nch_w = nch;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int o = __shfl_xor(nch_w, off);
+            nch_w = o > nch_w ? o : nch_w;
+        }
+        nch_w = __builtin_amdgcn_readfirstlane(nch_w);
 
         if (kGeoOnly) {
             if (valid) {
@@ -555,7 +622,9 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
             }
             account(A, valid, st, n);
         } else {
-            trace_transfer<kMode>(A, slot, lane, valid, pix, alpha, beta, st, n);
+            trace_transfer<kMode>(A, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
+            if (lane == 0)
+                for (int k = 0; k < nch_w; ++k) atomicExch(&A.chunk_flags[wchunks[k]], 0u);
         }
     }
 }

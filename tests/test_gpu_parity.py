@@ -207,9 +207,12 @@ def test_reduce_matches_oracle(ctx, adaf64_oracle):
     assert abs(flux[0] - fo2[0]) / fo2[0] <= FLUX_TOL
 
 
-def test_ragged_image_and_long_ray_path(ctx):
-    """A 37 x 23 image (ragged 8x8 tiles), with a tiny wave store so that most
-    rays take the long-ray kernel."""
+@pytest.mark.parametrize("chunks,expect_long", [("64", "none"), ("1", "any"), ("0", "some")])
+def test_ragged_image_and_long_ray_path(ctx, chunks, expect_long):
+    """A 37 x 23 image (ragged 8x8 tiles) with a 700-point wave slice, so that
+    most paths continue in chunks of the paged store (64 chunks: all of them,
+    no long rays), compete for a single chunk (some fall back to the long-ray
+    kernel) or, without chunks, all take the long-ray kernel."""
     cam = W.adaf_camera(37, fov=30.0)
     cam.update(ny=23, fov_y=20.0, seed=12345)
     w = {"camera": cam, "model": W.ADAF, "units": W.UNITS}
@@ -218,13 +221,20 @@ def test_ragged_image_and_long_ray_path(ctx):
     _compare_images(out["stokes"].cpu().numpy(), So, out["status"].cpu().numpy(), sto,
                     out["nsteps"].cpu().numpy(), nso)
     os.environ["KRT_PATH_CAP"] = "700"
+    os.environ["KRT_CHUNKS"] = chunks
     try:
         out2 = _gpu_image(ctx, w)
-        assert out2["stats"]["long_rays"] > 0
+        long_rays = out2["stats"]["long_rays"]
+        _log(f"chunks={chunks}: long rays {long_rays}, longest {int(nso.max())} steps")
+        if expect_long == "none":
+            assert long_rays == 0 and nso.max() > 700
+        elif expect_long == "some":
+            assert long_rays > 0
         _compare_images(out2["stokes"].cpu().numpy(), So, out2["status"].cpu().numpy(), sto,
                         out2["nsteps"].cpu().numpy(), nso)
     finally:
         del os.environ["KRT_PATH_CAP"]
+        del os.environ["KRT_CHUNKS"]
 
 
 def test_single_pixel_and_step_cap(ctx):
