@@ -93,7 +93,8 @@ KRT_HD void geo_rhs(double a, double m, const double y[7], double d[7]) {
 KRT_HD double rk4_step(double a, double m, double eps, double y[7], double& sn, double& cs) {
     double k[7], ks[7], yt[7];
     geo_rhs_sc(a, m, y, sn, cs, k);
-    const double h = -eps / (fabs(y[4]) / y[0] + fabs(y[5]) * fmax(1.0, fabs(cs / sn)) + fabs(y[6]));
+    const double h =
+        -eps * rcp_fast(fabs(y[4]) * rcp_fast(y[0]) + fabs(y[5]) * fmax(1.0, fabs(cs * rcp_fast(sn))) + fabs(y[6]));
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         ks[i] = k[i];
@@ -258,9 +259,9 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
         const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
         const double nu = A.cam.freq * (-Ku);
         const double bb = dot(g, p.b, p.b);
-        const double bn = bb > 0.0 ? sqrt(bb) : 0.0;
         const double cth =
-            bn > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (bn * (-Ku))
+            bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) * rsqrt_fast(bb) *
+                           rcp_fast(-Ku)
                      : 0.0;
         double c[8];
         const double seq = thermal_coefficients(A.btab, p.ne, p.thetae, p.B, nu, cth, c);
