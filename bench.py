@@ -90,13 +90,94 @@ def cpu_baseline(w, sample, snap_host=None):
                               "sample": f"every 8th pixel of that sample ({len(pix1)}), {dt1:.1f} s wall"}}
 
 
+def run_batch(args):
+    """The batched image library: 256 snapshot instances in <= 16 geodesic
+    groups, traced in one persistent launch per step; value = instance rays/s."""
+    import numpy as np
+    import torch
+    from paper_2302_02733_amd import krt
+    from paper_2302_02733_amd import workloads as W
+
+    f32 = args.precision == "fp32"
+    desc = W.snapshot_desc()
+    host = W.make_snapshot(desc, 7)
+    if f32:
+        host = host.astype(np.float32)
+    prims = torch.tensor(host, device="cuda")
+    groups, inst = W.batch_library()
+    for d in inst:
+        g = groups[d["group"]]
+        d["stokes"] = torch.empty((4, g["ny"], g["nx"]), dtype=torch.float64, device="cuda")
+    rays = sum(groups[d["group"]]["nx"] * groups[d["group"]]["ny"] for d in inst)
+    geo = sum(g["nx"] * g["ny"] for g in groups)
+    line = {}
+    with krt.Context(0) as ctx:
+        if f32:
+            ctx.set_precision(krt.PRECISION_FP32_TRANSFER)
+        ctx.set_units(W.UNITS)
+        ctx.set_model_snapshot(desc, prims)
+        if args.autotune:
+            t0 = time.perf_counter()
+            cfg = ctx.autotune(groups, inst)
+            print(f"tuned {cfg} in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        cfg = ctx.get_launch_config()
+        for _ in range(args.warmup):
+            ctx.trace_batch(groups, inst)
+            print("warmup step done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms = []
+        for k in range(args.steps):
+            st = ctx.trace_batch(groups, inst)
+            kms.append(st["kernel_ms"][0] + st["kernel_ms"][1])
+            print(f"step {k} done: {kms[-1]:.1f} ms in the tracers", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fluxes = []
+        for d in inst[:4]:
+            cam = dict(groups[d["group"]], freq_hz=d["freq_hz"])
+            fluxes.append(ctx.reduce(d["stokes"], cam)[0][0])
+        plain = None
+        if args.batch_plain:
+            # the plain tracer, instance by instance, same configuration
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for d in inst:
+                ctx.set_model_snapshot(dict(desc, M_unit_g=d["M_unit_g"], R_high=d["R_high"]), prims)
+                ctx.trace(dict(groups[d["group"]], freq_hz=d["freq_hz"]), stokes=d["stokes"], stats=False)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t1
+            plain = {"value": rays / tp, "unit": "instance rays/s", "seconds": tp}
+            print(f"plain instance by instance: {tp:.2f} s", file=sys.stderr, flush=True)
+    line = {
+        "metric": "instance rays/s, batched image library (shared geodesics, one persistent launch)",
+        "value": args.steps * rays / dt, "unit": "instance rays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if f32 else "f64", "data": "synthetic",
+        "config": {"workload": "batch256", "instances": len(inst), "groups": len(groups),
+                   "instance_pixels": rays, "geodesics": geo,
+                   "model": "synthetic GRMHD-like snapshot 288x128x128, a=0.94",
+                   "launch_config": cfg, "parallelism": "single GPU"},
+        "tracer_ms": sum(kms) / len(kms),
+        "flux_jy_first_instances": fluxes,
+        "plain_by_instance": plain,
+        "speedup_vs_plain": (args.steps * rays / dt) / plain["value"] if plain else None,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="adaf1024",
-                    choices=["adaf64", "adaf1024", "adaf4096", "snap48", "snap2048"])
+                    choices=["adaf64", "adaf1024", "adaf4096", "snap48", "snap2048", "batch256"])
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch256: pick the launch configuration with the library's tuner first")
+    ap.add_argument("--batch-plain", action="store_true",
+                    help="batch256: also time the plain tracer run instance by instance")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="pixels for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
@@ -111,6 +192,10 @@ def main():
         sys.exit(2)
     if args.flop_probe or args.copy_probe:
         run_probe("flop" if args.flop_probe else "copy", args.precision)
+        return
+
+    if args.workload == "batch256":
+        run_batch(args)
         return
 
     import numpy as np

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 2
+#define KRT_ABI_VERSION 3
 
 typedef enum {
     KRT_OK = 0,
@@ -200,6 +200,65 @@ krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint
  * d_nsteps ([ny][nx] int32, may be NULL). */
 krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes,
                            uint8_t* d_status, int32_t* d_nsteps, krt_stats* out_stats);
+
+/* ---- batched image libraries ---- */
+
+/* Launch configuration of the persistent tracers (context-wide; chosen by
+ * hand or by krt_autotune).  tile_w: pixels per row of the pixel tile one
+ * 64-lane wave traces, 64 / tile_w rows (4, 8, 16, 32 or 64; default 8);
+ * blocks_per_cu: blocks of 256 threads per compute unit in the persistent
+ * grid (0: as many as fit); path_cap: points per wave slice of the path store
+ * (0: KRT_PATH_CAP or 8192), longer paths continue in chunks; order (batches):
+ * 1 queues the groups with most instances first, 0 keeps the given order. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t tile_w;
+    int32_t blocks_per_cu;
+    int32_t path_cap;
+    int32_t order;
+} krt_launch_config;
+
+krt_status krt_set_launch_config(krt_ctx* ctx, const krt_launch_config* cfg);
+krt_status krt_get_launch_config(const krt_ctx* ctx, krt_launch_config* out);
+
+/* One image of a batch (the paper's motivation: libraries of many images of
+ * one model, Sec. 1 and Sec. 4).  group: index of the camera (geometry,
+ * resolution, step control) whose geodesics the image shares; freq_hz: its
+ * observing frequency; M_unit_g, R_high: snapshot mass unit and electron
+ * temperature ratio (0: the model's values; must be 0 for the ADAF model);
+ * d_stokes: [4][ny][nx] FP64 output of the group's resolution (device memory,
+ * caller-owned); d_status: [ny][nx] uint8 or NULL. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t group;
+    double freq_hz;
+    double M_unit_g;
+    double R_high;
+    double* d_stokes;
+    uint8_t* d_status;
+} krt_instance;
+
+/* Traces a batch of images in one persistent launch: each queue item is one
+ * tile of one group; its geodesics are integrated once (they do not depend on
+ * frequency or on the plasma normalisation) and the stored path is walked once
+ * per instance of the group.  Each image equals the one krt_trace would make
+ * for the group camera at the instance's frequency and plasma parameters.
+ * The groups' freq_hz fields are not used; all groups share the spin and mass
+ * factor.  out_stats (optional) counts instance rays.  Errors: KRT_E_INVAL,
+ * KRT_E_STATE, KRT_E_NOMEM, KRT_E_HIP. */
+krt_status krt_trace_batch(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups,
+                           const krt_instance* inst, int32_t ninst, krt_stats* out_stats);
+
+/* Launch-configuration tuner: times krt_trace_batch on a reduced form of the
+ * batch (one instance per group) for a set of candidate configurations
+ * (tile_w 8, 16, 32; blocks_per_cu 1, 2; path_cap 4096, 8192), sets the
+ * fastest on the context and returns it.  Results are cached in the text file
+ * cache_path (NULL: no cache) under a key made of the device name, its
+ * compute-unit count, the precision, the model and the batch's shape, so a
+ * later call with the same key only reads the file.  Synchronous. */
+krt_status krt_autotune(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups,
+                        const krt_instance* inst, int32_t ninst, const char* cache_path,
+                        krt_launch_config* out_cfg);
 
 /* Image reduction: total flux densities F_S = 1e23 dOmega sum_ij S_ij in Jy,
  * dOmega = (fov_x L / (nx D)) (fov_y L / (ny D)), L = G M / c^2, with

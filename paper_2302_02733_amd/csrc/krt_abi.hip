@@ -7,7 +7,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "krt.h"
 #include "krt_kernels.hpp"
@@ -44,7 +46,15 @@ struct krt_ctx {
     int long_slots = 0;
     int long_max_steps = -1;
     int32_t* overflow_list = nullptr;
+    int32_t* overflow_inst = nullptr;
     size_t overflow_cap = 0;
+    // launch configuration (tile shape, grid, slice size)
+    krt_launch_config cfg{sizeof(krt_launch_config), 8, 0, 0, 1};
+    // batch descriptors: device copy and pinned staging
+    void* batch_dev = nullptr;
+    size_t batch_dev_bytes = 0;
+    void* batch_host = nullptr;
+    size_t batch_host_bytes = 0;
     // counters: [0] tile queue, [1] overflow count (unsigned); then 8 x u64
     unsigned* work = nullptr;
     double* red_partial = nullptr;
@@ -131,6 +141,8 @@ int env_int(const char* name, int dflt) {
     return v ? std::atoi(v) : dflt;
 }
 
+void fill_f32(krt_ctx* ctx, double nu, TraceArgs& A);
+
 TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     TraceArgs A;
     std::memset(&A, 0, sizeof(A));
@@ -170,11 +182,24 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     A.adaf.h = ctx->adaf.h_over_r;
     A.adaf.risco = isco(cam->a);
     A.btab = ctx->btab;
+    fill_f32(ctx, cam->freq_hz, A);
+    const int tw = ctx->cfg.tile_w;
+    A.tile_w = tw;
+    A.tiles_x = (cam->nx + tw - 1) / tw;
+    A.nbatch = A.tiles_x * ((cam->ny + 64 / tw - 1) / (64 / tw));
+    A.queue = ctx->work;
+    A.overflow_count = ctx->work + 1;
+    A.counters = reinterpret_cast<unsigned long long*>(ctx->work + 2);
+    return A;
+}
+
+// Constants of the FP32 transfer operators for camera frequency nu and the
+// model parameters already in A, folded in FP64.
+void fill_f32(krt_ctx* ctx, double nu, TraceArgs& A) {
     {
-        // constants of the FP32 transfer operators, folded in FP64
         F32Consts& C = A.f32;
-        const double nu = cam->freq_hz, L = A.L_cm, e2 = kE * kE;
-        C.a = (float)cam->a;
+        const double L = A.L_cm, e2 = kE * kE;
+        C.a = (float)A.cam.a;
         C.m = (float)A.cam.m;
         C.cJ = (float)(e2 * nu / (2.0 * std::sqrt(3.0) * kC));
         C.cRV = (float)(2.0 * e2 / (kME * kC * nu * nu));
@@ -205,12 +230,6 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
             C.mpme = (float)(kMP / kME);
         }
     }
-    A.tiles_x = (cam->nx + 7) / 8;
-    A.nbatch = A.tiles_x * ((cam->ny + 7) / 8);
-    A.queue = ctx->work;
-    A.overflow_count = ctx->work + 1;
-    A.counters = reinterpret_cast<unsigned long long*>(ctx->work + 2);
-    return A;
 }
 
 // Sizes the wave-synchronous store: one slice of `cap` points for every
@@ -218,11 +237,12 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
 // as fit on the device, within the KRT_POOL_GB budget).  The store only grows.
 template <int kMode>
 krt_status ensure_pool(krt_ctx* ctx) {
-    const int cap = env_int("KRT_PATH_CAP", 8192);
+    const int cap = ctx->cfg.path_cap > 0 ? ctx->cfg.path_cap : env_int("KRT_PATH_CAP", 8192);
     const double budget_gb = (double)env_int("KRT_POOL_GB", 96);
     int per_cu = 0;
     KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<kMode>, 256, 0));
     if (per_cu < 1) per_cu = 1;
+    if (ctx->cfg.blocks_per_cu > 0 && ctx->cfg.blocks_per_cu < per_cu) per_cu = ctx->cfg.blocks_per_cu;
     int blocks = per_cu * ctx->cu_count;
     const size_t per_block = (size_t)4 * 64 * cap * 8 * sizeof(double);
     const size_t budget = (size_t)(budget_gb * 1073741824.0);
@@ -300,14 +320,18 @@ krt_status ensure_long(krt_ctx* ctx, int max_steps, size_t npix) {
         ctx->long_bytes = (size_t)slots * per;
     }
     if (ctx->overflow_cap < npix) {
-        if (ctx->overflow_list) {
-            KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            KRT_HIP(ctx, hipFree(ctx->overflow_list));
-            ctx->overflow_list = nullptr;
-        }
-        if (hipMalloc(&ctx->overflow_list, npix * sizeof(int32_t)) != hipSuccess) {
-            ctx->overflow_list = nullptr;
+        KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->overflow_list) KRT_HIP(ctx, hipFree(ctx->overflow_list));
+        if (ctx->overflow_inst) KRT_HIP(ctx, hipFree(ctx->overflow_inst));
+        ctx->overflow_list = nullptr;
+        ctx->overflow_inst = nullptr;
+        ctx->overflow_cap = 0;
+        if (hipMalloc(&ctx->overflow_list, npix * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&ctx->overflow_inst, npix * sizeof(int32_t)) != hipSuccess) {
             (void)hipGetLastError();
+            if (ctx->overflow_list) (void)hipFree(ctx->overflow_list);
+            ctx->overflow_list = nullptr;
+            ctx->overflow_inst = nullptr;
             return fail(ctx, KRT_E_NOMEM, "cannot allocate the overflow list");
         }
         ctx->overflow_cap = npix;
@@ -315,13 +339,13 @@ krt_status ensure_long(krt_ctx* ctx, int max_steps, size_t npix) {
     return KRT_OK;
 }
 
-krt_status fill_stats(krt_ctx* ctx, const krt_camera* cam, krt_stats* s) {
+krt_status fill_stats(krt_ctx* ctx, int64_t rays, krt_stats* s) {
     KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, ctx->work + 2, 8 * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, ctx->stream));
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const unsigned long long* c = reinterpret_cast<const unsigned long long*>(ctx->host_buf);
     s->struct_size = sizeof(krt_stats);
-    s->rays = (int64_t)cam->nx * cam->ny;
+    s->rays = rays;
     s->total_steps = (int64_t)c[0];
     for (int k = 0; k < 5; ++k) s->status_count[k] = (int64_t)c[1 + k];
     s->max_steps_seen = (int32_t)c[6];
@@ -418,6 +442,9 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->long_pool) (void)hipFree(ctx->long_pool);
     if (ctx->overflow_list) (void)hipFree(ctx->overflow_list);
     if (ctx->work) (void)hipFree(ctx->work);
+    if (ctx->overflow_inst) (void)hipFree(ctx->overflow_inst);
+    if (ctx->batch_dev) (void)hipFree(ctx->batch_dev);
+    if (ctx->batch_host) (void)hipHostFree(ctx->batch_host);
     if (ctx->chunk_pool) (void)hipFree(ctx->chunk_pool);
     if (ctx->chunk_flags) (void)hipFree(ctx->chunk_flags);
     if (ctx->red_partial) (void)hipFree(ctx->red_partial);
@@ -528,13 +555,261 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
         hipLaunchKernelGGL(trace_long<kModeF64>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
-    if (out_stats) return fill_stats(ctx, cam, out_stats);
+    if (out_stats) return fill_stats(ctx, (int64_t)cam->nx * cam->ny, out_stats);
     return KRT_OK;
 }
 
 krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
                      krt_stats* out_stats) {
     return krt_trace_steps(ctx, cam, d_stokes, d_status, nullptr, out_stats);
+}
+
+krt_status krt_set_launch_config(krt_ctx* ctx, const krt_launch_config* cfg) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!cfg || cfg->struct_size != sizeof(krt_launch_config)) return fail(ctx, KRT_E_INVAL, "bad config struct");
+    const int tw = cfg->tile_w;
+    if (!(tw == 4 || tw == 8 || tw == 16 || tw == 32 || tw == 64))
+        return fail(ctx, KRT_E_INVAL, "tile_w must be 4, 8, 16, 32 or 64");
+    if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 16) return fail(ctx, KRT_E_INVAL, "blocks_per_cu must be 0..16");
+    if (cfg->path_cap != 0 && (cfg->path_cap < 64 || cfg->path_cap > 65536))
+        return fail(ctx, KRT_E_INVAL, "path_cap must be 0 or 64..65536");
+    if (cfg->order != 0 && cfg->order != 1) return fail(ctx, KRT_E_INVAL, "order must be 0 or 1");
+    ctx->cfg = *cfg;
+    return KRT_OK;
+}
+
+krt_status krt_get_launch_config(const krt_ctx* ctx, krt_launch_config* out) {
+    if (!ctx || !out) return KRT_E_INVAL;
+    *out = ctx->cfg;
+    return KRT_OK;
+}
+
+krt_status krt_trace_batch(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups, const krt_instance* inst,
+                           int32_t ninst, krt_stats* out_stats) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!groups || ngroups < 1 || ngroups > 4096) return fail(ctx, KRT_E_INVAL, "need 1..4096 groups");
+    if (!inst || ninst < 1 || ninst > (1 << 20)) return fail(ctx, KRT_E_INVAL, "need 1..2^20 instances");
+    krt_status st = check_ready(ctx, &groups[0]);
+    if (st != KRT_OK) return st;
+    for (int g = 0; g < ngroups; ++g) {
+        const std::string m = check_camera(&groups[g]);
+        if (!m.empty()) return fail(ctx, KRT_E_INVAL, "group " + std::to_string(g) + ": " + m);
+        if (groups[g].a != groups[0].a || groups[g].mass_factor != groups[0].mass_factor)
+            return fail(ctx, KRT_E_INVAL, "all groups must share the spin and mass factor");
+    }
+    std::vector<int> count(ngroups, 0);
+    int64_t rays = 0;
+    for (int q = 0; q < ninst; ++q) {
+        const krt_instance& I = inst[q];
+        if (I.struct_size != sizeof(krt_instance)) return fail(ctx, KRT_E_INVAL, "instance struct_size mismatch");
+        if (I.group < 0 || I.group >= ngroups) return fail(ctx, KRT_E_INVAL, "instance group out of range");
+        if (!std::isfinite(I.freq_hz) || !(I.freq_hz > 0.0)) return fail(ctx, KRT_E_INVAL, "instance freq_hz must be > 0");
+        if (!std::isfinite(I.M_unit_g) || I.M_unit_g < 0.0 || !std::isfinite(I.R_high) || I.R_high < 0.0)
+            return fail(ctx, KRT_E_INVAL, "instance M_unit_g and R_high must be finite and >= 0");
+        if (ctx->model != kModelSnapshot && (I.M_unit_g != 0.0 || I.R_high != 0.0))
+            return fail(ctx, KRT_E_INVAL, "M_unit_g and R_high apply to the snapshot model only (use 0)");
+        if (!I.d_stokes) return fail(ctx, KRT_E_INVAL, "instance d_stokes is NULL");
+        ++count[I.group];
+        rays += (int64_t)groups[I.group].nx * groups[I.group].ny;
+    }
+    if (rays > (int64_t)INT32_MAX) return fail(ctx, KRT_E_INVAL, "more than 2^31 instance pixels");
+    // queue order of the groups: most instances first (their tiles cost most)
+    std::vector<int> gorder(ngroups);
+    for (int g = 0; g < ngroups; ++g) gorder[g] = g;
+    if (ctx->cfg.order == 1)
+        std::stable_sort(gorder.begin(), gorder.end(), [&](int x, int y) { return count[x] > count[y]; });
+    std::vector<int> gpos(ngroups);
+    for (int k = 0; k < ngroups; ++k) gpos[gorder[k]] = k;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    const bool f32 = ctx->precision == KRT_PRECISION_FP32_TRANSFER;
+    if ((st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx)) != KRT_OK) return st;
+    if ((st = ensure_chunks(ctx)) != KRT_OK) return st;
+    int max_steps = 1;
+    for (int g = 0; g < ngroups; ++g) max_steps = std::max(max_steps, (int)groups[g].max_steps);
+    if ((st = ensure_long(ctx, max_steps, (size_t)rays)) != KRT_OK) return st;
+
+    // descriptors: groups in queue order, instances sorted by group
+    const int tw = ctx->cfg.tile_w, thh = 64 / tw;
+    std::vector<GroupDev> G(ngroups);
+    int items = 0;
+    std::vector<int> ibegin(ngroups + 1, 0);
+    for (int k = 0; k < ngroups; ++k) ibegin[k + 1] = ibegin[k] + count[gorder[k]];
+    for (int k = 0; k < ngroups; ++k) {
+        const krt_camera& c = groups[gorder[k]];
+        GroupDev& d = G[k];
+        std::memset(&d, 0, sizeof(d));
+        d.cam = camera_desc(&c);
+        d.eps = c.eps;
+        d.r_stop = c.mass_factor == 0 ? 1e-6 : 1.05 * horizon(c.a, 1.0);
+        d.max_steps = c.max_steps;
+        d.tiles_x = (c.nx + tw - 1) / tw;
+        d.item_begin = items;
+        items += d.tiles_x * ((c.ny + thh - 1) / thh);
+        d.item_end = items;
+        d.inst_begin = ibegin[k];
+        d.inst_end = ibegin[k + 1];
+    }
+    std::vector<InstDev> I(ninst);
+    std::vector<int> fill(ngroups, 0);
+    for (int q = 0; q < ninst; ++q) {
+        const int k = gpos[inst[q].group];
+        const int slotq = ibegin[k] + fill[k]++;
+        krt_camera c = groups[inst[q].group];
+        c.freq_hz = inst[q].freq_hz;
+        TraceArgs T = base_args(ctx, &c);
+        if (ctx->model == kModelSnapshot) {
+            const double L = T.L_cm;
+            if (inst[q].M_unit_g > 0.0) {
+                T.snap.rho_unit = inst[q].M_unit_g / (L * L * L);
+                T.snap.B_unit = kC * std::sqrt(4.0 * kPi * T.snap.rho_unit);
+            }
+            if (inst[q].R_high > 0.0) T.snap.Rhigh = inst[q].R_high;
+            fill_f32(ctx, c.freq_hz, T);
+        }
+        InstDev& d = I[slotq];
+        std::memset(&d, 0, sizeof(d));
+        d.freq = c.freq_hz;
+        d.fac0 = T.fac0;
+        d.rho_unit = T.snap.rho_unit;
+        d.B_unit = T.snap.B_unit;
+        d.Rhigh = T.snap.Rhigh;
+        d.f32 = T.f32;
+        d.stokes = inst[q].d_stokes;
+        d.status = inst[q].d_status;
+        d.group = k;
+    }
+    const size_t gbytes = (size_t)ngroups * sizeof(GroupDev), ibytes = (size_t)ninst * sizeof(InstDev);
+    const size_t ioff = (gbytes + 255) / 256 * 256, need = ioff + ibytes;
+    if (ctx->batch_host_bytes < need || ctx->batch_dev_bytes < need) {
+        KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->batch_host) KRT_HIP(ctx, hipHostFree(ctx->batch_host));
+        if (ctx->batch_dev) KRT_HIP(ctx, hipFree(ctx->batch_dev));
+        ctx->batch_host = ctx->batch_dev = nullptr;
+        ctx->batch_host_bytes = ctx->batch_dev_bytes = 0;
+        if (hipHostMalloc(&ctx->batch_host, need) != hipSuccess || hipMalloc(&ctx->batch_dev, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, KRT_E_NOMEM, "cannot allocate the batch descriptors");
+        }
+        ctx->batch_host_bytes = ctx->batch_dev_bytes = need;
+    } else {
+        // the staging buffer may still feed an earlier batch's copy
+        KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    char* hb = static_cast<char*>(ctx->batch_host);
+    std::memcpy(hb, G.data(), gbytes);
+    std::memcpy(hb + ioff, I.data(), ibytes);
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->batch_dev, ctx->batch_host, need, hipMemcpyHostToDevice, ctx->stream));
+
+    TraceArgs A = base_args(ctx, &groups[gorder[0]]);
+    A.groups = reinterpret_cast<const GroupDev*>(ctx->batch_dev);
+    A.inst = reinterpret_cast<const InstDev*>(static_cast<char*>(ctx->batch_dev) + ioff);
+    A.ngroups = ngroups;
+    A.nbatch = items;
+    A.max_steps = max_steps;
+    A.pool = ctx->pool;
+    A.cap = ctx->pool_cap;
+    A.chunk_pool = ctx->chunk_pool;
+    A.chunk_flags = ctx->chunk_flags;
+    A.nchunks = ctx->nchunks;
+    A.long_pool = ctx->long_pool;
+    A.long_slots = ctx->long_slots;
+    A.overflow_list = ctx->overflow_list;
+    A.overflow_inst = ctx->overflow_inst;
+    if (ctx->nchunks > 0)
+        KRT_HIP(ctx, hipMemsetAsync(ctx->chunk_flags, 0, (size_t)ctx->nchunks * sizeof(unsigned), ctx->stream));
+    KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
+    if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
+    if (f32)
+        hipLaunchKernelGGL(trace_batch<kModeF32>, dim3(ctx->launch_blocks), dim3(256), 0, ctx->stream, A);
+    else
+        hipLaunchKernelGGL(trace_batch<kModeF64>, dim3(ctx->launch_blocks), dim3(256), 0, ctx->stream, A);
+    KRT_HIP(ctx, hipGetLastError());
+    if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    if (f32)
+        hipLaunchKernelGGL(trace_long<kModeF32>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+    else
+        hipLaunchKernelGGL(trace_long<kModeF64>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+    KRT_HIP(ctx, hipGetLastError());
+    if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+    if (out_stats) return fill_stats(ctx, rays, out_stats);
+    return KRT_OK;
+}
+
+krt_status krt_autotune(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups, const krt_instance* inst,
+                        int32_t ninst, const char* cache_path, krt_launch_config* out_cfg) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!groups || ngroups < 1 || !inst || ninst < 1) return fail(ctx, KRT_E_INVAL, "empty batch");
+    // cache key: device, precision, model and the batch's shape
+    hipDeviceProp_t prop;
+    KRT_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    std::string key = std::string(prop.gcnArchName) + "|" + std::to_string(ctx->cu_count) + "|p" +
+                      std::to_string(ctx->precision) + "|m" + std::to_string(ctx->model);
+    std::vector<int> per(ngroups, 0);
+    for (int q = 0; q < ninst; ++q)
+        if (inst[q].group >= 0 && inst[q].group < ngroups) ++per[inst[q].group];
+    for (int g = 0; g < ngroups; ++g)
+        key += "|" + std::to_string(groups[g].nx) + "x" + std::to_string(groups[g].ny) + "i" + std::to_string(per[g]);
+    unsigned long long h = 1469598103934665603ULL;  // FNV-1a
+    for (unsigned char ch : key) {
+        h ^= ch;
+        h *= 1099511628211ULL;
+    }
+    char hkey[32];
+    std::snprintf(hkey, sizeof(hkey), "%016llx", h);
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char k[64];
+            krt_launch_config c{sizeof(krt_launch_config), 8, 0, 0, 1};
+            double ms = 0.0;
+            bool found = false;
+            while (std::fscanf(f, "%63s %d %d %d %d %lf", k, &c.tile_w, &c.blocks_per_cu, &c.path_cap, &c.order, &ms) == 6)
+                if (std::strcmp(k, hkey) == 0) found = true, ctx->cfg = c;
+            std::fclose(f);
+            if (found) {
+                if (out_cfg) *out_cfg = ctx->cfg;
+                return KRT_OK;
+            }
+        }
+    }
+    // reduced batch: the first instance of every group
+    std::vector<krt_instance> red;
+    std::vector<char> seen(ngroups, 0);
+    for (int q = 0; q < ninst; ++q) {
+        const int g = inst[q].group;
+        if (g >= 0 && g < ngroups && !seen[g]) {
+            seen[g] = 1;
+            red.push_back(inst[q]);
+        }
+    }
+    const krt_launch_config saved = ctx->cfg;
+    krt_launch_config best = saved;
+    double best_ms = 1e300;
+    const int tws[] = {8, 16, 32}, bpcs[] = {1, 2}, caps[] = {4096, 8192};
+    for (int tw : tws)
+        for (int bpc : bpcs)
+            for (int cap : caps) {
+                krt_launch_config c{sizeof(krt_launch_config), tw, bpc, cap, 1};
+                ctx->cfg = c;
+                krt_stats stt;
+                stt.struct_size = sizeof(krt_stats);
+                const krt_status e = krt_trace_batch(ctx, groups, ngroups, red.data(), (int32_t)red.size(), &stt);
+                if (e != KRT_OK) {
+                    ctx->cfg = saved;
+                    return e;
+                }
+                const double ms = stt.kernel_ms[0] + stt.kernel_ms[1];
+                if (ms < best_ms) best_ms = ms, best = c;
+            }
+    ctx->cfg = best;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d %d %d %.3f\n", hkey, best.tile_w, best.blocks_per_cu, best.path_cap, best.order,
+                         best_ms);
+            std::fclose(f);
+        }
+    }
+    if (out_cfg) *out_cfg = best;
+    return KRT_OK;
 }
 
 krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_state,

@@ -39,7 +39,8 @@ struct TraceArgs {
     double* pool;
     int cap;            // stored points per lane slice
     int tiles_x, nbatch;
-    unsigned* queue;    // [0]: next 8x8 tile
+    int tile_w;         // pixels per tile row; a tile is tile_w x (64 / tile_w)
+    unsigned* queue;    // [0]: next tile (or batch item)
     // paged extension of the wave store: chunks of `cap` points x 64 lanes,
     // taken by a wave whose rays outgrow its slice, returned after the tile
     double* chunk_pool;
@@ -49,7 +50,13 @@ struct TraceArgs {
     double* long_pool;
     int long_slots;
     int32_t* overflow_list;
+    int32_t* overflow_inst;  // batch mode: instance of each overflow entry
+    int inst_id;
     unsigned* overflow_count;
+    // batch mode: geodesic groups and image instances (null in plain mode)
+    const struct GroupDev* groups;
+    const struct InstDev* inst;
+    int ngroups;
     // outputs
     double* stokes;     // [4][ny][nx]
     uint8_t* status;    // [ny][nx] or null
@@ -468,72 +475,129 @@ __device__ __forceinline__ const double* point_addr(const TraceArgs& A, const do
     return A.chunk_pool + (size_t)c * A.cap * 512 + ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * 8;
 }
 
-// Transfer phase of one 8x8 tile (all lanes on the same point index, far
-// end first), output and accounting.
+// Transfer phase of one tile (all lanes on the same point index, far end
+// first), output and accounting.  Rays that overflowed the store are queued
+// for the long-ray kernel (with their instance in batch mode).
 template <int kMode>
 __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot, const int* wchunks,
-                                               int lane,
-                                               bool valid, int pix, double alpha, double beta,
+                                               int lane, bool valid, int pix, double alpha, double beta,
                                                uint8_t st, int n) {
-    {
-        if (valid && st == kOverflow) {
-            const unsigned k = atomicAdd(A.overflow_count, 1u);
-            A.overflow_list[k] = pix;
-        }
-        account(A, valid, st, n);
+    if (valid && st == kOverflow) {
+        const unsigned k = atomicAdd(A.overflow_count, 1u);
+        A.overflow_list[k] = pix;
+        if (A.overflow_inst) A.overflow_inst[k] = A.inst_id;
+    }
+    account(A, valid, st, n);
 
-        // ---- transfer: all lanes on the same point index, far end first ----
-        const bool xfer = valid && st != kOverflow;
-        // a path whose last point is non-finite or lies on the polar axis (where
-        // the coordinate frame is singular) is transferred over the points before it
-        const int n_end = xfer ? ((st == kNonFinite || st == kAxis) ? n - 1 : n) : -1;
-        int nred = n_end;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int o = __shfl_xor(nred, off);
-            nred = o > nred ? o : nred;
-        }
-        const int nmax = __builtin_amdgcn_readfirstlane(nred);
-        XferState xs;
-        Coh N;
-        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
-        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
-        for (int m = nmax; m >= 0; --m) {
-            if (m <= n_end) {
-                double pt[8];
-                load_point(point_addr(A, slot, wchunks, m, lane), pt);
-                TraceArgs L = A;
-                launder_transfer(L);
-                if (kMode == kModeF32)
-                    transfer_point_f32(L, pt, m, m == n_end, xs, N);
-                else
-                    transfer_point(L, pt, m, m == n_end, xs, N);
-            }
-        }
-        if (xfer) {
-            double S[4];
+    // ---- transfer: all lanes on the same point index, far end first ----
+    const bool xfer = valid && st != kOverflow;
+    // a path whose last point is non-finite or lies on the polar axis (where
+    // the coordinate frame is singular) is transferred over the points before it
+    const int n_end = xfer ? ((st == kNonFinite || st == kAxis) ? n - 1 : n) : -1;
+    int nred = n_end;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(nred, off);
+        nred = o > nred ? o : nred;
+    }
+    const int nmax = __builtin_amdgcn_readfirstlane(nred);
+    XferState xs;
+    Coh N;
+    for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
+    for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+    for (int m = nmax; m >= 0; --m) {
+        if (m <= n_end) {
+            double pt[8];
+            load_point(point_addr(A, slot, wchunks, m, lane), pt);
             TraceArgs L = A;
-            launder_camera(L.cam);
-            camera_output(L, alpha, beta, N, S);
-            write_pixel(A, pix, S, st, n);
+            launder_transfer(L);
+            if (kMode == kModeF32)
+                transfer_point_f32(L, pt, m, m == n_end, xs, N);
+            else
+                transfer_point(L, pt, m, m == n_end, xs, N);
         }
+    }
+    if (xfer) {
+        double S[4];
+        TraceArgs L = A;
+        launder_camera(L.cam);
+        camera_output(L, alpha, beta, N, S);
+        write_pixel(A, pix, S, st, n);
     }
 }
 
-// ---------------------------------------------------------------------------
-// Persistent wave-synchronous tracer.  kMode: FP64 transfer, FP32 transfer
-// operators, or (kModeGeo) the geodesic phase only, writing
-// the end state (no store, no transfer).
-// ---------------------------------------------------------------------------
-// Two waves per SIMD (at most 256 registers per lane): with one, the FP64
-// dependency chains of a single wave leave the vector ALU idle.
+// Pixel of a lane in tile `tile` of an image with tiles_x tiles per row; a
+// tile is tile_w pixels wide and 64 / tile_w rows high.
+__device__ __forceinline__ void tile_pixel(int tiles_x, int tile_w, int tile, int lane, int& i, int& j) {
+    const int th = 64 / tile_w;
+    i = (tile % tiles_x) * tile_w + lane % tile_w;
+    j = (tile / tiles_x) * th + lane / tile_w;
+}
+
+// Geodesic phase of one tile: camera launch and RK4 steps in lockstep, every
+// point stored in the wave's slice, then in chunks of the paged store (kStore),
+// or only the end state kept.  Returns the number of chunks the wave holds.
+template <bool kStore>
+__device__ __forceinline__ int geodesic_phase(const TraceArgs& A, bool valid, int i, int j, double* slot,
+                                              int* wchunks, size_t wave, int lane, double& alpha,
+                                              double& beta, double y[7], double& hlast, uint8_t& st,
+                                              int& n) {
+    alpha = 0.0;
+    beta = 0.0;
+    {
+        CameraDesc C = A.cam;
+        launder_camera(C);
+        pixel_position(C, valid ? i : 0, valid ? j : 0, alpha, beta);
+        double X[4], K[4];
+        camera_launch(C, alpha, beta, X, K);
+        y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
+        y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
+    }
+    double sn, cs;
+    sincos(y[1], &sn, &cs);
+    if (kStore && valid) store_point(slot + (size_t)lane * 8, y, 0.0);
+
+    st = valid ? kRunning : kEscaped;
+    n = 0;
+    hlast = 0.0;
+    // store of points [cstart, cstart + cap): the slice, then chunks; the
+    // lanes still stepping all sit at the same n, so nch, cstart and cbase
+    // agree among them
+    int nch = 0, cstart = 0;
+    double* cbase = slot;
+    while (st == kRunning) {
+        const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
+        ++n;
+        hlast = h;
+        if (kStore) {
+            if (n == cstart + A.cap) {
+                const int id = (nch < kMaxChunks && A.nchunks > 0)
+                                   ? take_chunk(A, wchunks, nch, (unsigned)wave * 7u + (unsigned)nch)
+                                   : -1;
+                if (id < 0) {  // no chunk: the long-ray kernel redoes these rays
+                    st = kOverflow;
+                    continue;
+                }
+                ++nch;
+                cstart += A.cap;
+                cbase = A.chunk_pool + (size_t)id * A.cap * 512;
+            }
+            store_point(cbase + ((size_t)(n - cstart) * 64 + lane) * 8, y, h);
+        }
+        st = stop_test(A, y, h, n, sn);
+    }
+    int nch_w = nch;
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(nch_w, off);
+        nch_w = o > nch_w ? o : nch_w;
+    }
+    return __builtin_amdgcn_readfirstlane(nch_w);
+}
+
+// The Bessel-ratio table (15 KiB in FP64, 7.5 KiB in FP32) is read at every
+// transfer point with lane-dependent panels: every block stages it in LDS.
 template <int kMode>
-__global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
-    constexpr bool kGeoOnly = kMode == kModeGeo;
-    // The Bessel-ratio table (15 KiB in FP64, 7.5 KiB in FP32) is read at
-    // every transfer point with lane-dependent panels: serve it from LDS.
+__device__ __forceinline__ void stage_table(TraceArgs& A, double* s_btab, float* s_btab_f) {
     constexpr int kTab = kBesPanels * 2 * kBesCoef;
-    __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
-    __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
     if (kMode == kModeF64) {
         for (int k = threadIdx.x; k < kTab; k += blockDim.x) s_btab[k] = A.btab[k];
         __syncthreads();
@@ -543,6 +607,22 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
         __syncthreads();
         A.btab_f = s_btab_f;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent wave-synchronous tracer.  kMode: FP64 transfer, FP32 transfer
+// operators, or (kModeGeo) the geodesic phase only, writing the end state (no
+// store, no transfer).  Two waves per SIMD (at most 256 registers per lane):
+// with one, the FP64 dependency chains of a single wave leave the vector ALU
+// idle.
+// ---------------------------------------------------------------------------
+template <int kMode>
+__global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
+    constexpr bool kGeoOnly = kMode == kModeGeo;
+    constexpr int kTab = kBesPanels * 2 * kBesCoef;
+    __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
+    __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
+    stage_table<kMode>(A, s_btab, s_btab_f);
     const int lane = threadIdx.x & 63;
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
@@ -553,66 +633,17 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
         // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
         // as a scalar, so the loop exit below is wave-uniform.
         const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
-        const int batch = __builtin_amdgcn_readfirstlane((int)ticket);
-        if (batch >= A.nbatch) break;
-        const int i = (batch % A.tiles_x) * 8 + (lane & 7);
-        const int j = (batch / A.tiles_x) * 8 + (lane >> 3);
+        const int tile = __builtin_amdgcn_readfirstlane((int)ticket);
+        if (tile >= A.nbatch) break;
+        int i, j;
+        tile_pixel(A.tiles_x, A.tile_w, tile, lane, i, j);
         const bool valid = i < A.cam.nx && j < A.cam.ny;
         const int pix = j * A.cam.nx + i;
-
-        double alpha = 0.0, beta = 0.0;
-        double y[7];
-        {
-            CameraDesc C = A.cam;
-            launder_camera(C);
-            pixel_position(C, valid ? i : 0, valid ? j : 0, alpha, beta);
-            double X[4], K[4];
-            camera_launch(C, alpha, beta, X, K);
-            y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
-            y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
-        }
-        double sn, cs;
-        sincos(y[1], &sn, &cs);
-        if (!kGeoOnly && valid) store_point(slot + (size_t)lane * 8, y, 0.0);
-
-        // ---- backward geodesic, one step per lane per iteration ----
-        uint8_t st = valid ? kRunning : kEscaped;
-        int n = 0;
-        double hlast = 0.0;
-        // store of points [cstart, cstart + cap): the slice, then chunks; the
-        // lanes still stepping all sit at the same n, so nch, cstart and cbase
-        // agree among them
-        int nch = 0, cstart = 0;
-        double* cbase = slot;
-        while (st == kRunning) {
-            const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
-            ++n;
-            hlast = h;
-            if (!kGeoOnly) {
-                if (n == cstart + A.cap) {
-                    const int id = (nch < kMaxChunks && A.nchunks > 0)
-                                       ? take_chunk(A, wchunks, nch, (unsigned)wave * 7u + (unsigned)nch)
-                                       : -1;
-                    if (id < 0) {  // no chunk: the long-ray kernel redoes these rays
-                        st = kOverflow;
-                        continue;
-                    }
-                    ++nch;
-                    cstart += A.cap;
-                    cbase = A.chunk_pool + (size_t)id * A.cap * 512;
-                }
-                store_point(cbase + ((size_t)(n - cstart) * 64 + lane) * 8, y, h);
-            }
-            st = stop_test(A, y, h, n, sn);
-        }
-        // chunks this wave holds for the tile
-        int nch_w = nch;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int o = __shfl_xor(nch_w, off);
-            nch_w = o > nch_w ? o : nch_w;
-        }
-        nch_w = __builtin_amdgcn_readfirstlane(nch_w);
-
+        double alpha, beta, hlast, y[7];
+        uint8_t st;
+        int n;
+        const int nch_w =
+            geodesic_phase<!kGeoOnly>(A, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y, hlast, st, n);
         if (kGeoOnly) {
             if (valid) {
                 double* e = A.end_state + (size_t)pix * 8;
@@ -630,8 +661,109 @@ __global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched image library: geodesic groups (one camera geometry and resolution
+// each) and image instances (frequency, snapshot mass unit and R_high, output
+// image) of those groups.  One queue item is one tile of one group: the wave
+// traces the tile's geodesics once and walks the stored path once per
+// instance of the group.
+// ---------------------------------------------------------------------------
+struct GroupDev {
+    CameraDesc cam;           // geometry (cam.freq unused)
+    double eps, r_stop;
+    int max_steps;
+    int tiles_x;
+    int item_begin, item_end; // queue items (tiles) of the group
+    int inst_begin, inst_end; // its instances in the instance array
+};
+
+struct InstDev {
+    double freq, fac0;
+    double rho_unit, B_unit, Rhigh;  // snapshot model
+    F32Consts f32;
+    double* stokes;
+    uint8_t* status;
+    int group;
+};
+
+// Copy of a descriptor that all lanes of the wave load from the same address,
+// moved into scalar registers word by word (the kernel writes global memory,
+// so the compiler cannot prove the descriptor invariant and loads it into
+// vector registers).
+template <class T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    T out;
+    const int* src = reinterpret_cast<const int*>(&v);
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+
+KRT_HD void apply_group(TraceArgs& L, const GroupDev& G) {
+    L.cam = G.cam;
+    L.eps = G.eps;
+    L.r_stop = G.r_stop;
+    L.max_steps = G.max_steps;
+    L.tiles_x = G.tiles_x;
+}
+
+KRT_HD void apply_instance(TraceArgs& L, const InstDev& I, int q) {
+    L.cam.freq = I.freq;
+    L.fac0 = I.fac0;
+    L.snap.rho_unit = I.rho_unit;
+    L.snap.B_unit = I.B_unit;
+    L.snap.Rhigh = I.Rhigh;
+    L.f32 = I.f32;
+    L.stokes = I.stokes;
+    L.status = I.status;
+    L.nsteps = nullptr;
+    L.inst_id = q;
+}
+
+template <int kMode>
+__global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
+    constexpr int kTab = kBesPanels * 2 * kBesCoef;
+    __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
+    __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
+    stage_table<kMode>(A, s_btab, s_btab_f);
+    const int lane = threadIdx.x & 63;
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
+    __shared__ int s_chunks[4][kMaxChunks];
+    int* wchunks = s_chunks[threadIdx.x >> 6];
+    for (;;) {
+        const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
+        const int item = __builtin_amdgcn_readfirstlane((int)ticket);
+        if (item >= A.nbatch) break;
+        int g = 0;
+        while (g < A.ngroups - 1 && item >= __builtin_amdgcn_readfirstlane(A.groups[g].item_end)) ++g;
+        const GroupDev G = wave_uniform(A.groups[g]);
+        TraceArgs Ag = A;
+        apply_group(Ag, G);
+        int i, j;
+        tile_pixel(G.tiles_x, A.tile_w, item - G.item_begin, lane, i, j);
+        const bool valid = i < G.cam.nx && j < G.cam.ny;
+        const int pix = j * G.cam.nx + i;
+        double alpha, beta, hlast, y[7];
+        uint8_t st;
+        int n;
+        const int nch_w =
+            geodesic_phase<true>(Ag, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y, hlast, st, n);
+        for (int q = G.inst_begin; q < G.inst_end; ++q) {
+            TraceArgs Ai = Ag;
+            apply_instance(Ai, wave_uniform(A.inst[q]), q);
+            trace_transfer<kMode>(Ai, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
+        }
+        if (lane == 0)
+            for (int k = 0; k < nch_w; ++k) atomicExch(&A.chunk_flags[wchunks[k]], 0u);
+    }
+}
+
 // Rays longer than the wave-synchronous store: one ray per lane with a
-// full-length private store ([point][8]); lanes loop over the overflow list.
+// full-length private store ([point][8]); lanes loop over the overflow list
+// (entries of batch instances carry their instance).
 template <int kMode>
 __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
     __shared__ float s_btab_f[kMode == kModeF32 ? kBesPanels * 2 * kBesCoef : 1];
@@ -646,11 +778,19 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
     const unsigned stride = gridDim.x * blockDim.x;
     double* path = A.long_pool + (size_t)tid * (size_t)(A.max_steps + 1) * 8;
     for (unsigned k = tid; k < total; k += stride) {
+        TraceArgs R = A;
+        if (A.overflow_inst) {
+            const int q = A.overflow_inst[k];
+            const InstDev& I = A.inst[q];
+            apply_group(R, A.groups[I.group]);
+            apply_instance(R, I, q);
+        }
         const int pix = A.overflow_list[k];
-        const int i = pix % A.cam.nx, j = pix / A.cam.nx;
+        const int i = pix % R.cam.nx, j = pix / R.cam.nx;
         double alpha, beta, y[7];
-        CameraDesc C = A.cam;
-        launder_camera(C);
+        // the parameters can differ from lane to lane here (batch instances),
+        // so they stay in vector registers and are not laundered
+        const CameraDesc C = R.cam;
         pixel_position(C, i, j, alpha, beta);
         {
             double X[4], K[4];
@@ -664,10 +804,10 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         uint8_t st = kRunning;
         int n = 0;
         while (st == kRunning) {
-            const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
+            const double h = rk4_step(R.cam.a, R.cam.m, R.eps, y, sn, cs);
             ++n;
             store_point(path + (size_t)n * 8, y, h);
-            st = stop_test(A, y, h, n, sn);
+            st = stop_test(R, y, h, n, sn);
         }
         const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
         XferState xs;
@@ -675,19 +815,14 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         for (int m = n_end; m >= 0; --m) {
             double pt[8];
             load_point(path + (size_t)m * 8, pt);
-            TraceArgs L = A;
-            launder_transfer(L);
             if (kMode == kModeF32)
-                transfer_point_f32(L, pt, m, m == n_end, xs, N);
+                transfer_point_f32(R, pt, m, m == n_end, xs, N);
             else
-                transfer_point(L, pt, m, m == n_end, xs, N);
+                transfer_point(R, pt, m, m == n_end, xs, N);
         }
         double S[4];
-        launder_camera(C);
-        TraceArgs L = A;
-        L.cam = C;
-        camera_output(L, alpha, beta, N, S);
-        write_pixel(A, pix, S, st, n);
+        camera_output(R, alpha, beta, N, S);
+        write_pixel(R, pix, S, st, n);
         // the wave-synchronous pass counted this ray as overflow; count it now
         atomicAdd(&A.counters[0], (unsigned long long)n);
         atomicAdd(&A.counters[1 + st], 1ULL);

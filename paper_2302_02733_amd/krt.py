@@ -67,6 +67,23 @@ class Stats(ctypes.Structure):
                 "long_rays": self.long_rays, "kernel_ms": list(self.kernel_ms)}
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("tile_w", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("path_cap", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"tile_w": self.tile_w, "blocks_per_cu": self.blocks_per_cu,
+                "path_cap": self.path_cap, "order": self.order}
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("group", ctypes.c_int32),
+                ("freq_hz", ctypes.c_double), ("M_unit_g", ctypes.c_double),
+                ("R_high", ctypes.c_double), ("d_stokes", ctypes.c_void_p),
+                ("d_status", ctypes.c_void_p)]
+
+
 # Every symbol include/krt.h declares, with (restype, argtypes).
 _P = ctypes.c_void_p
 _SIGS = {
@@ -89,6 +106,12 @@ _SIGS = {
     "krt_bessel_ratios": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "krt_mueller_step": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_double, _P]),
     "krt_set_precision": (ctypes.c_int, [_P, ctypes.c_int]),
+    "krt_set_launch_config": (ctypes.c_int, [_P, ctypes.POINTER(LaunchConfig)]),
+    "krt_get_launch_config": (ctypes.c_int, [_P, ctypes.POINTER(LaunchConfig)]),
+    "krt_trace_batch": (ctypes.c_int, [_P, ctypes.POINTER(Camera), ctypes.c_int32, ctypes.POINTER(Instance),
+                                       ctypes.c_int32, ctypes.POINTER(Stats)]),
+    "krt_autotune": (ctypes.c_int, [_P, ctypes.POINTER(Camera), ctypes.c_int32, ctypes.POINTER(Instance),
+                                    ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(LaunchConfig)]),
 }
 
 PRECISION_FP64 = 0
@@ -202,6 +225,54 @@ class Context:
         self._snapshot = prims
         dtype = DTYPE_F64 if prims.dtype == torch.float64 else DTYPE_F32
         self._check(lib().krt_set_model_snapshot(self.h, ctypes.byref(d), _ptr(prims), dtype))
+
+    def set_launch_config(self, tile_w=8, blocks_per_cu=0, path_cap=0, order=1):
+        c = LaunchConfig(ctypes.sizeof(LaunchConfig), tile_w, blocks_per_cu, path_cap, order)
+        self._check(lib().krt_set_launch_config(self.h, ctypes.byref(c)))
+
+    def get_launch_config(self):
+        c = LaunchConfig()
+        self._check(lib().krt_get_launch_config(self.h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def _batch_args(self, groups, instances):
+        cams = (Camera * len(groups))(*[make_camera(g) for g in groups])
+        arr = (Instance * len(instances))()
+        for k, d in enumerate(instances):
+            g = groups[d["group"]]
+            st = d["stokes"]
+            _dev(st, self.device)
+            if st.dtype != torch.float64 or tuple(st.shape) != (4, g["ny"], g["nx"]):
+                raise ValueError("instance stokes must be float64 [4][ny][nx] of its group")
+            status = d.get("status")
+            if status is not None:
+                _dev(status, self.device)
+                if status.dtype != torch.uint8 or tuple(status.shape) != (g["ny"], g["nx"]):
+                    raise ValueError("instance status must be uint8 [ny][nx]")
+            arr[k] = Instance(ctypes.sizeof(Instance), d["group"], d["freq_hz"], d.get("M_unit_g", 0.0),
+                              d.get("R_high", 0.0), st.data_ptr(),
+                              status.data_ptr() if status is not None else None)
+        return cams, arr
+
+    def trace_batch(self, groups, instances, stats=True):
+        """groups: camera dicts (shared geodesics); instances: dicts with group,
+        freq_hz, M_unit_g, R_high (snapshot; 0 = the model's), stokes
+        ([4][ny][nx] float64 device tensor) and optionally status."""
+        cams, arr = self._batch_args(groups, instances)
+        self._stream()
+        s = Stats()
+        s.struct_size = ctypes.sizeof(Stats)
+        self._check(lib().krt_trace_batch(self.h, cams, len(groups), arr, len(instances),
+                                          ctypes.byref(s) if stats else None))
+        return s.as_dict() if stats else None
+
+    def autotune(self, groups, instances, cache_path=None):
+        cams, arr = self._batch_args(groups, instances)
+        self._stream()
+        c = LaunchConfig()
+        self._check(lib().krt_autotune(self.h, cams, len(groups), arr, len(instances),
+                                       cache_path.encode() if cache_path else None, ctypes.byref(c)))
+        return c.as_dict()
 
     def set_precision(self, precision):
         """PRECISION_FP64 or PRECISION_FP32_TRANSFER (FP32 transfer operators,

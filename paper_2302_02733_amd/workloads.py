@@ -146,3 +146,51 @@ def make_snapshot(desc, seed=7, a=0.94):
     P[..., 0:2] *= 10 ** 1.5
     P[..., 5:8] *= 10 ** 0.75
     return np.ascontiguousarray(P)
+
+
+# ---------------------------------------------------------------------------
+# Batched image library on the snapshot: instances drawn with SplitMix64
+# (seed 11): mass unit 10^U(17,20) g, R_high in {1, 10, 40, 160}, inclination
+# in {20, 60, 120, 160} deg, frequency in {86, 230, 345} GHz, resolution in
+# {128, 256, 512, 1024}; geodesics are shared by the instances of one
+# (inclination, resolution) group.
+# ---------------------------------------------------------------------------
+
+_MASK64 = (1 << 64) - 1
+
+
+def _splitmix64(seed):
+    state = seed & _MASK64
+    while True:
+        state = (state + 0x9E3779B97F4A7C15) & _MASK64
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        yield z ^ (z >> 31)
+
+
+def batch_library(n_inst=256, seed=11, resolutions=(128, 256, 512, 1024)):
+    """Returns (groups, instances): groups are snapshot cameras, one per
+    (inclination, resolution) in order of first appearance; instances are dicts
+    with group, freq_hz, M_unit_g, R_high."""
+    rng = _splitmix64(seed)
+
+    def u01():
+        return (next(rng) >> 11) * 2.0 ** -53
+
+    def choice(seq):
+        return seq[min(int(u01() * len(seq)), len(seq) - 1)]
+
+    groups, index, instances = [], {}, []
+    for _ in range(n_inst):
+        m_unit = 10.0 ** (17.0 + 3.0 * u01())
+        r_high = choice((1.0, 10.0, 40.0, 160.0))
+        incl = choice((20.0, 60.0, 120.0, 160.0))
+        freq = choice((86e9, 230e9, 345e9))
+        n = choice(tuple(resolutions))
+        key = (incl, n)
+        if key not in index:
+            index[key] = len(groups)
+            groups.append(snapshot_camera(n, incl_deg=incl))
+        instances.append({"group": index[key], "freq_hz": freq, "M_unit_g": m_unit, "R_high": r_high})
+    return groups, instances

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(krt):
     missing = [s for s in declared_symbols() if not hasattr(L, s)]
     assert not missing
     assert set(declared_symbols()) == set(krt._SIGS)
-    assert krt.lib().krt_abi_version() == 2
+    assert krt.lib().krt_abi_version() == 3
 
 
 def test_struct_layouts_match_header(krt, tmp_path):
@@ -45,7 +45,8 @@ def test_struct_layouts_match_header(krt, tmp_path):
     import ctypes
     import subprocess
     structs = {"krt_camera": krt.Camera, "krt_units": krt.Units, "krt_adaf": krt.Adaf,
-               "krt_snapshot_desc": krt.SnapshotDesc, "krt_stats": krt.Stats}
+               "krt_snapshot_desc": krt.SnapshotDesc, "krt_stats": krt.Stats,
+               "krt_launch_config": krt.LaunchConfig, "krt_instance": krt.Instance}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "krt.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
@@ -83,3 +84,22 @@ def test_invalid_cameras_rejected_on_host(krt, bad):
 def test_valid_camera_accepted(krt):
     assert krt.check_camera(_cam()) == ""
     assert krt.check_camera(_cam(mass_factor=0, a=0.0)) == ""
+
+
+def test_batch_library_shape():
+    """The batched-library workload: 256 instances, <= 16 geodesic groups keyed
+    by (inclination, resolution), about 89M instance pixels over 5.6M
+    geodesics, parameters in their stated ranges, reproducible from the seed."""
+    from paper_2302_02733_amd import workloads as W
+    groups, inst = W.batch_library()
+    assert len(inst) == 256 and len(groups) <= 16
+    keys = {(g["incl_deg"], g["nx"]) for g in groups}
+    assert len(keys) == len(groups)
+    pix = sum(groups[i["group"]]["nx"] * groups[i["group"]]["ny"] for i in inst)
+    assert 80e6 < pix < 100e6
+    assert sum(g["nx"] * g["ny"] for g in groups) <= 16 * (128**2 + 256**2 + 512**2 + 1024**2) / 4 * 4
+    for i in inst:
+        assert 1e17 <= i["M_unit_g"] <= 1e20
+        assert i["R_high"] in (1.0, 10.0, 40.0, 160.0)
+        assert i["freq_hz"] in (86e9, 230e9, 345e9)
+    assert W.batch_library() == (groups, inst)
