@@ -11,6 +11,8 @@
 // slice are finished by a per-lane kernel with a full-length store.
 #pragma once
 
+#include <type_traits>
+
 #include "krt_device.hpp"
 #include "krt_f32.hpp"
 
@@ -223,6 +225,16 @@ struct XferState {
     double Dnext;
 };
 
+// The FP32-operator transfer keeps the coherency matrix after point n in
+// FP64 and the transport rate there, F(A_n, N), in FP32 (2^160-scaled): the
+// predictor N + D_n F and the corrector N + D_n/2 (F + F(A_{n-1}, Ns)) are
+// formed from them at point n-1 (48 instead of 64 registers of state).
+struct XferStateF {
+    Coh N;
+    CohF F;
+    double Dnext;
+};
+
 KRT_HD bool plasma_at(const TraceArgs& A, double r, double th, double ph, const Metric& g,
                       Plasma& p) {
     if (A.model == kModelSnapshot) return snapshot_plasma(A.snap, A.cam.a, A.cam.m, r, th, ph, g, p);
@@ -305,7 +317,7 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
 // formed in FP32 (scaled by 2^160) and added in FP64.  The radiative update
 // adds the coherency matrix of the Stokes increment on the fluid legs.
 KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bool first,
-                               XferState& st, Coh& N) {
+                               XferStateF& st, Coh& N) {
     const F32Consts& C = A.f32;
     // sin and cos of theta from an argument reduced in FP64 toward the nearer pole
     const double thd = pt[1];
@@ -329,14 +341,19 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bo
         for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
     } else {
         Dnext = st.Dnext;
-        CohF Nf, F;
-        to_scaled_f(st.Ns, Nf);
-        transport_rhs_f(Ac, Nf, F);
+        CohF Ns, F;
+        to_scaled_f(st.N, Ns);
+        const float Df = (float)Dnext;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Ns.R[k] += Df * st.F.R[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Ns.I[k] += Df * st.F.I[k];
+        transport_rhs_f(Ac, Ns, F);
         const double hh = 0.5 * Dnext * kIScaleInv;
 #pragma unroll
-        for (int k = 0; k < 10; ++k) N.R[k] = st.H.R[k] + hh * (double)F.R[k];
+        for (int k = 0; k < 10; ++k) N.R[k] = st.N.R[k] + hh * ((double)st.F.R[k] + (double)F.R[k]);
 #pragma unroll
-        for (int k = 0; k < 6; ++k) N.I[k] = st.H.I[k] + hh * (double)F.I[k];
+        for (int k = 0; k < 6; ++k) N.I[k] = st.N.I[k] + hh * ((double)st.F.I[k] + (double)F.I[k]);
     }
 
     PlasmaF p;
@@ -375,20 +392,10 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bo
     }
 
     if (n > 0) {
-        CohF Nf, F;
+        CohF Nf;
         to_scaled_f(N, Nf);
-        transport_rhs_f(Ac, Nf, F);
-        const double hh = 0.5 * Dn * kIScaleInv, hf = Dn * kIScaleInv;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            st.H.R[k] = N.R[k] + hh * (double)F.R[k];
-            st.Ns.R[k] = N.R[k] + hf * (double)F.R[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            st.H.I[k] = N.I[k] + hh * (double)F.I[k];
-            st.Ns.I[k] = N.I[k] + hf * (double)F.I[k];
-        }
+        transport_rhs_f(Ac, Nf, st.F);
+        st.N = N;
         st.Dnext = Dn;
     }
 }
@@ -500,7 +507,7 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
         nred = o > nred ? o : nred;
     }
     const int nmax = __builtin_amdgcn_readfirstlane(nred);
-    XferState xs;
+    typename std::conditional<kMode == kModeF32, XferStateF, XferState>::type xs;
     Coh N;
     for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
     for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
@@ -510,7 +517,7 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
             load_point(point_addr(A, slot, wchunks, m, lane), pt);
             TraceArgs L = A;
             launder_transfer(L);
-            if (kMode == kModeF32)
+            if constexpr (kMode == kModeF32)
                 transfer_point_f32(L, pt, m, m == n_end, xs, N);
             else
                 transfer_point(L, pt, m, m == n_end, xs, N);
@@ -810,12 +817,12 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
             st = stop_test(R, y, h, n, sn);
         }
         const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
-        XferState xs;
+        typename std::conditional<kMode == kModeF32, XferStateF, XferState>::type xs;
         Coh N;
         for (int m = n_end; m >= 0; --m) {
             double pt[8];
             load_point(path + (size_t)m * 8, pt);
-            if (kMode == kModeF32)
+            if constexpr (kMode == kModeF32)
                 transfer_point_f32(R, pt, m, m == n_end, xs, N);
             else
                 transfer_point(R, pt, m, m == n_end, xs, N);
