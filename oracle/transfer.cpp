@@ -16,7 +16,10 @@
  *  - radiative update: project N on the fluid tetrad legs e1, e2
  *    (I = N11 + N22, Q = N11 - N22, U = 2 Re N12, V = -2 Im N12), apply the
  *    exact constant-coefficient solution of dS/dlam = J - K S over w_n,
- *    rebuild N from S on the same legs;
+ *    rebuild N from S on the same legs; where every coefficient is zero (no
+ *    plasma) the update is the identity on S and N is left as it is (the
+ *    rebuild would only drop components along K, which no later projection
+ *    sees);
  *  - fluid tetrad: e0 = u, e3 = unit vector along K + (K.u) u (equal to
  *    (K + (K.u) u)/(-K.u) for null K), e2 along the part of b
  *    orthogonal to u and e3 (fallback d_theta, then d_r), e1 completing a
@@ -239,8 +242,6 @@ static void radiative_update(const or_camera* cam, double L_cm, const or_model* 
     metric(a, m, r, th, g);
     Plasma p;
     if (!plasma(model, snap, a, m, r, th, ph, L_cm, &p)) return;  /* no valid fluid frame */
-    FluidFrame F;
-    fluid_frame(g, p.u, K, p.b, &F);
 
     double Ku = dot(g, K, p.u);
     double nu = cam->freq_hz * (-Ku);
@@ -260,6 +261,15 @@ static void radiative_update(const or_camera* cam, double L_cm, const or_model* 
         if (model->kind == OR_MODEL_SLAB_PLASMA && r < model->slab_radius)
             for (int k = 0; k < 3; ++k) coef[k] += model->slab_jextra[k];
     }
+    /* No emission, absorption or rotation (e.g. no plasma): the update is the
+     * identity on the Stokes vector, and projecting N on the fluid legs and
+     * rebuilding it would only drop its components along K, which no later
+     * projection sees; the point leaves N as it is. */
+    bool zero = true;
+    for (int k = 0; k < 8; ++k) zero = zero && coef[k] == 0.0;
+    if (zero) return;
+    FluidFrame F;
+    fluid_frame(g, p.u, K, p.b, &F);
     double S[4], S2[4];
     project(g, N, F.e1, F.e2, S);
     mueller_step(coef, S, w, S2);

@@ -235,9 +235,15 @@ struct XferStateF {
     double Dnext;
 };
 
+// Plasma for the radiative update; false where the update leaves N unchanged:
+// no timelike flow, or (snapshot) beyond the emission radius, where n_e = 0
+// makes every coefficient zero.
 KRT_HD bool plasma_at(const TraceArgs& A, double r, double th, double ph, const Metric& g,
                       Plasma& p) {
-    if (A.model == kModelSnapshot) return snapshot_plasma(A.snap, A.cam.a, A.cam.m, r, th, ph, g, p);
+    if (A.model == kModelSnapshot) {
+        if (r > A.snap.rmax) return false;
+        return snapshot_plasma(A.snap, A.cam.a, A.cam.m, r, th, ph, g, p);
+    }
     return adaf_plasma(A.adaf, A.cam.a, A.cam.m, r, g, p);
 }
 
@@ -284,14 +290,18 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
                      : 0.0;
         double c[8];
         const double seq = thermal_coefficients(A.btab, p.ne, p.thetae, p.B, nu, cth, c);
-        const double fac = A.fac0 * nu;
-        double e1[4], l1[4], e2[4], l2[4];
-        fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
-        double S[4];
-        coh_project(N, l1, l2, S);
-        mueller_thermal(seq, fac * c[3], fac * c[4], fac * c[5], fac * c[6], fac * c[7],
-                        0.5 * (Dn + Dnext), S);
-        coh_rebuild(N, S, e1, e2);
+        // no absorption or rotation (no plasma): the update is the identity
+        // and N stays as it is
+        if (c[3] != 0.0 || c[4] != 0.0 || c[5] != 0.0 || c[6] != 0.0 || c[7] != 0.0) {
+            const double fac = A.fac0 * nu;
+            double e1[4], l1[4], e2[4], l2[4];
+            fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+            double S[4];
+            coh_project(N, l1, l2, S);
+            mueller_thermal(seq, fac * c[3], fac * c[4], fac * c[5], fac * c[6], fac * c[7],
+                            0.5 * (Dn + Dnext), S);
+            coh_rebuild(N, S, e1, e2);
+        }
     }
 
     if (n > 0) {
@@ -362,8 +372,10 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bo
         const SnapDesc& q = A.snap;
         double X2 = (pt[2] - q.x3s) / q.dx3 - 0.5;
         X2 -= q.n3 * floor(X2 / q.n3);
-        ok = q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
-                       : snapshot_plasma_f(C, q.prims, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p);
+        // no plasma beyond the emission radius (n_e = 0: every coefficient zero)
+        ok = pt[0] <= q.rmax &&
+             (q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
+                        : snapshot_plasma_f(C, q.prims, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p));
     } else {
         ok = adaf_plasma_f(C, r, g, p);
     }
@@ -379,16 +391,18 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bo
                       : 0.0f;
         float co[5];
         const float seq = thermal_f(C, A.btab_f, p.ne, p.thetae, p.B, gz, cth, co);
-        // invariant coefficients (x L nu / nu_cam) times the step length
-        const float w = (float)(0.5 * (Dn + Dnext)) * C.L * gz;
-        float e1[4], l1[4], e2[4], l2[4];
-        fluid_legs_f(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
-        CohF Nf;
-        to_scaled_f(N, Nf);
-        float S[4], dS[4];
-        coh_project_f(Nf, l1, l2, S);
-        mueller_delta_f(seq, co[0] * w, co[1] * w, co[2] * w, co[3] * w, co[4] * w, S, dS);
-        coh_add_delta_f(N, dS, e1, e2);
+        if (co[0] != 0.0f || co[1] != 0.0f || co[2] != 0.0f || co[3] != 0.0f || co[4] != 0.0f) {
+            // invariant coefficients (x L nu / nu_cam) times the step length
+            const float w = (float)(0.5 * (Dn + Dnext)) * C.L * gz;
+            float e1[4], l1[4], e2[4], l2[4];
+            fluid_legs_f(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+            CohF Nf;
+            to_scaled_f(N, Nf);
+            float S[4], dS[4];
+            coh_project_f(Nf, l1, l2, S);
+            mueller_delta_f(seq, co[0] * w, co[1] * w, co[2] * w, co[3] * w, co[4] * w, S, dS);
+            coh_add_delta_f(N, dS, e1, e2);
+        }
     }
 
     if (n > 0) {
@@ -949,10 +963,9 @@ __global__ void hook_plasma(TraceArgs A, int64_t n, double a, double m, const do
     Metric g;
     metric_eval(a, m, r, th, g);
     Plasma p;
-    TraceArgs B = A;
-    B.cam.a = a;
-    B.cam.m = m;
-    const bool ok = plasma_at(B, r, th, ph, g, p);
+    // the model itself (plasma_at also skips points the transfer leaves alone)
+    const bool ok = A.model == kModelSnapshot ? snapshot_plasma(A.snap, a, m, r, th, ph, g, p)
+                                              : adaf_plasma(A.adaf, a, m, r, g, p);
     double* o = out + k * 12;
     o[0] = p.ne; o[1] = p.thetae; o[2] = p.B;
     for (int q = 0; q < 4; ++q) {
