@@ -90,17 +90,37 @@ KRT_HD void geo_rhs(double a, double m, const double y[7], double d[7]) {
     geo_rhs_sc(a, m, y, sn, cs, d);
 }
 
+// sin and cos of theta + d from sin and cos of theta: the angle-addition
+// formulas with Taylor series of sin d and cos d (through d^9 and d^10: below
+// 1e-18 for |d| < 0.1, the step rule keeps the stage offsets near 1e-2), or a
+// fresh sincos for a larger offset.
+KRT_HD void sincos_shift(double th, double sn, double cs, double d, double& s2, double& c2) {
+    if (fabs(d) < 0.1) {
+        const double d2 = d * d;
+        const double sd = d * (1.0 - d2 * (1.0 / 6.0) * (1.0 - d2 * (1.0 / 20.0) * (1.0 - d2 * (1.0 / 42.0) *
+                                                                                  (1.0 - d2 * (1.0 / 72.0)))));
+        const double cd = 1.0 - d2 * 0.5 * (1.0 - d2 * (1.0 / 12.0) * (1.0 - d2 * (1.0 / 30.0) *
+                                                                        (1.0 - d2 * (1.0 / 56.0) *
+                                                                                   (1.0 - d2 * (1.0 / 90.0)))));
+        s2 = sn * cd + cs * sd;
+        c2 = cs * cd - sn * sd;
+    } else {
+        sincos(th + d, &s2, &c2);
+    }
+}
+
 // One classical RK4 step with
 //   |dlam| = eps / (|K^r|/r + |K^theta| max(1, |cot theta|) + |K^phi|),
 // dlam < 0: relative change of r, change of theta and phi, and relative change
 // of sin(theta) bounded by eps, so steps shrink near the polar axis where the
 // coordinate frame turns quickly.  (sn, cs) hold sin and cos of theta at the
 // start point on entry and at the end point on return, so each point's sincos
-// serves the stop test after the step and the first stage of the next one.
+// serves the stop test after the step and the first stage of the next one;
+// the inner stages take theirs by angle addition from the start point's.
 // The stage sum k1 + 2 k2 + 2 k3 + k4 is accumulated as the stages are made.
 // Returns dlam.
 KRT_HD double rk4_step(double a, double m, double eps, double y[7], double& sn, double& cs) {
-    double k[7], ks[7], yt[7];
+    double k[7], ks[7], yt[7], s2, c2;
     geo_rhs_sc(a, m, y, sn, cs, k);
     const double h =
         -eps * rcp_fast(fabs(y[4]) * rcp_fast(y[0]) + fabs(y[5]) * fmax(1.0, fabs(cs * rcp_fast(sn))) + fabs(y[6]));
@@ -109,19 +129,22 @@ KRT_HD double rk4_step(double a, double m, double eps, double y[7], double& sn, 
         ks[i] = k[i];
         yt[i] = y[i] + 0.5 * h * k[i];
     }
-    geo_rhs(a, m, yt, k);
+    sincos_shift(y[1], sn, cs, 0.5 * h * k[1], s2, c2);
+    geo_rhs_sc(a, m, yt, s2, c2, k);
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         ks[i] += 2.0 * k[i];
         yt[i] = y[i] + 0.5 * h * k[i];
     }
-    geo_rhs(a, m, yt, k);
+    sincos_shift(y[1], sn, cs, 0.5 * h * k[1], s2, c2);
+    geo_rhs_sc(a, m, yt, s2, c2, k);
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         ks[i] += 2.0 * k[i];
         yt[i] = y[i] + h * k[i];
     }
-    geo_rhs(a, m, yt, k);
+    sincos_shift(y[1], sn, cs, h * k[1], s2, c2);
+    geo_rhs_sc(a, m, yt, s2, c2, k);
 #pragma unroll
     for (int i = 0; i < 7; ++i) y[i] += h / 6.0 * (ks[i] + k[i]);
     sincos(y[1], &sn, &cs);
