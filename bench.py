@@ -24,18 +24,17 @@ if ROOT not in sys.path:
 # RK4 step plus one transfer point), FMA counted as two: measured with the
 # rocprofv3 FP64 VALU instruction counters on a divergence-free launch
 # (bench.py --flop-probe, every lane tracing the same ray), 64 lanes per wave
-# instruction.  See the design doc (measurement).
+# instruction.
 FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "3100.9"))
 # Same for the FP32-operator transfer (FP64 plus FP32 VALU operations; both run
-# at the same per-lane rate without packed FP32), None until measured.
+# at the same per-lane rate without packed FP32).
 FLOPS_PER_RAY_STEP_F32 = 2854.3
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 
 # HBM bytes per ray-step of trace_waves on the 1024^2 ADAF image: rocprofv3
 # FETCH_SIZE and WRITE_SIZE of one launch, each scaled by what the counter
-# reads for a copy of known size, divided by the launch's ray-steps (None
-# until measured on the current kernel).
-TRAFFIC_BYTES_PER_RAY_STEP = None
+# reads for a copy of known size, divided by the launch's ray-steps.
+TRAFFIC_BYTES_PER_RAY_STEP = 128.4
 TRAFFIC_WORKLOAD = "adaf1024"
 HBM_PEAK_GBS = 8000.0
 
