@@ -20,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 ESCAPED, CAPTURED, STEP_CAP, NONFINITE, AXIS = 0, 1, 2, 3, 4
+DIST_KAPPA, DIST_THERMAL = 0, 1
 MODEL_ADAF, MODEL_SLAB_PLASMA, MODEL_SLAB_FIXED, MODEL_SNAPSHOT = 0, 1, 2, 3
 
 
@@ -114,6 +115,14 @@ def lib():
         L.or_reduce.restype = None
         L.or_reduce.argtypes = [ctypes.POINTER(Camera), ctypes.POINTER(Units), _D, _D, _D]
         L.or_max_threads.restype = ctypes.c_int
+        L.or_synchrotron_kernels.restype = None
+        L.or_synchrotron_kernels.argtypes = [ctypes.c_int64, _D, _D]
+        L.or_bessel_k.restype = None
+        L.or_bessel_k.argtypes = [ctypes.c_int64, ctypes.c_double, _D, _D, _D]
+        L.or_kappa_integrals.restype = None
+        L.or_kappa_integrals.argtypes = [ctypes.c_int32, ctypes.c_int64, _D, _D, ctypes.c_int32]
+        L.or_kappa_coefficients.restype = None
+        L.or_kappa_coefficients.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 6 + [_D]
         _lib = L
     return _lib
 
@@ -320,3 +329,36 @@ def reduce(cam, units, stokes):
 
 def max_threads():
     return lib().or_max_threads()
+
+
+def synchrotron_kernels(X):
+    """F, G, H of the nonthermal module at the points X: array [n, 3]."""
+    X = np.ascontiguousarray(X, dtype=np.float64).ravel()
+    out = np.empty((X.size, 3))
+    lib().or_synchrotron_kernels(X.size, _ptr(X), _ptr(out))
+    return out
+
+
+def bessel_k(nu, x):
+    """K_nu(x) and int_x^inf K_nu from the oracle's integral representations."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    k = np.empty_like(x)
+    ki = np.empty_like(x)
+    lib().or_bessel_k(x.size, nu, _ptr(x), _ptr(k), _ptr(ki))
+    return k, ki
+
+
+def kappa_integrals(inputs, dist=DIST_KAPPA, threads=0):
+    """The eight dimensionless integrals (I_F, I_G, I_H, A_F, A_G, A_H, R_Q, R_V)
+    at rows (kappa, w, X) of inputs: array [n, 8]."""
+    a = np.ascontiguousarray(inputs, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((a.shape[0], 8))
+    lib().or_kappa_integrals(dist, a.shape[0], _ptr(a), _ptr(out), threads)
+    return out
+
+
+def kappa_coefficients(kappa, ne, w, B, nu, cos_thb, dist=DIST_KAPPA):
+    """Fluid-frame coefficients (cgs) j_I j_Q j_V a_I a_Q a_V r_Q r_V."""
+    out = np.empty(8)
+    lib().or_kappa_coefficients(dist, kappa, ne, w, B, nu, cos_thb, _ptr(out))
+    return out

@@ -139,6 +139,21 @@ void or_reduce(const or_camera* cam, const or_units* units, const double* stokes
                double flux_jy[4], double* imax);
 int or_max_threads(void);
 
+/* Electron distributions of the nonthermal module. */
+#define OR_DIST_KAPPA 0
+#define OR_DIST_THERMAL 1
+/* Synchrotron functions F, G, H at n points X: out[3i..3i+2]. */
+void or_synchrotron_kernels(int64_t n, const double* X, double* out);
+/* K_nu(x) and int_x^inf K_nu(s) ds at n points. */
+void or_bessel_k(int64_t n, double nu, const double* x, double* k, double* ki);
+/* The eight dimensionless integrals I_F I_G I_H A_F A_G A_H R_Q R_V of the
+ * distribution at n points in[3i..3i+2] = (kappa, w, X). */
+void or_kappa_integrals(int32_t dist, int64_t n, const double* in, double* out, int32_t threads);
+/* Fluid-frame coefficients (cgs) of the distribution, layout of
+ * or_thermal_coefficients. */
+void or_kappa_coefficients(int32_t dist, double kappa, double ne, double w, double B, double nu,
+                           double cos_thb, double out[8]);
+
 #ifdef __cplusplus
 }
 #endif

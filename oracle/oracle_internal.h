@@ -65,6 +65,9 @@ int validate_model(const or_model* model, const or_snapshot* snap, const or_came
 
 /* coefficients.cpp */
 void bessel_ratios(double x, double* k0k2, double* k1k2);
+void kappa_coefficients(int dist, double kappa, double ne, double w, double B, double nu,
+                        double cos_thb, double out[8]);
+void kappa_integrals(int dist, double kappa, double w, double X, double out[8]);
 void thermal_coefficients(double ne, double thetae, double B, double nu, double cos_thb,
                           double out[8]);
 
