@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 3
+#define KRT_ABI_VERSION 4
 
 typedef enum {
     KRT_OK = 0,
@@ -305,6 +305,85 @@ krt_status krt_bessel_ratios(krt_ctx* ctx, int64_t n, const double* d_x, double*
  * d_out [n][4] out. */
 krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S,
                             double w, double* d_out);
+
+
+/* ---- Nonthermal (kappa) electrons ----------------------------------------
+ * Sec. 2.1 lists the electron distribution among the model inputs and Sec. 4
+ * names nonthermal electrons as the next step.  The coefficients of an
+ * isotropic kappa distribution N(g) ~ g sqrt(g^2-1) (1 + (g-1)/(kappa w))^-(kappa+1)
+ * (width w in place of Theta_e) follow from ultrarelativistic synchrotron
+ * theory as eight dimensionless integrals over the Lorentz factor g, which
+ * depend on (kappa, w, X = nu / nu_c) only, nu_c = 1.5 nu_B sin(theta_B) w^2:
+ *   I_F = <F(Xg)>, I_G = <G(Xg)>, I_H = <H(Xg)/g>            (emission I, Q, V)
+ *   A_F, A_G, A_H: the same with the Einstein-relation weight   (absorption)
+ *   R_Q = <(2g - 1/g) Xg/(1+Xg)>, R_V = <acosh g / (g sqrt(g^2-1))>  (rotation)
+ * with Xg = X w^2 / g^2 and the synchrotron functions F = X int_X K_5/3,
+ * G = X K_2/3, H = X K_1/3 + int_X K_1/3.  The fluid-frame coefficients are
+ * j_I = n_e c0 I_F, j_Q = n_e c0 I_G, j_V = n_e c0 (4/3) cot(theta_B) I_H,
+ * alpha_S = (same with A_S) / (2 nu^2 m_e), c0 = sqrt3 e^3 B sin(theta_B) /
+ * (4 pi m_e c^2), rho_Q and rho_V with the thermal prefactors times R_Q, R_V.
+ */
+
+/* Exact integrator: d_in [n][3] = (kappa, w, X) with kappa > 0, w > 0, X > 0
+ * (device, doubles); d_out [n][8] the integrals above (device).  Trapezoid rule
+ * in ln(g - 1), synchrotron functions from a Chebyshev table built on first use
+ * (relative accuracy ~1e-10). */
+krt_status krt_kappa_integrals(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out);
+
+/* Constant-coefficient Stokes update for a general emissivity (test hook):
+ * d_coef [n][8] = (J_I, J_Q, J_V, A_I, A_Q, A_V, R_Q, R_V) with
+ * A_I >= sqrt(A_Q^2 + A_V^2), d_S [n][4] in, d_out [n][4] = exp(-K w) S +
+ * (int_0^w exp(-K s) ds) J over path length w >= 0. */
+krt_status krt_mueller_general(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S, double w,
+                               double* d_out);
+
+/* Learned surrogate of the eight integrals: an MLP 4 -> 64 -> 64 -> 64 -> 8
+ * (SiLU) on the features ((kappa - 5.5)/2.5, log10 w - 1, (log10 X - 2)/4,
+ * cos theta_B) whose outputs z give log10 I_k = mu_k + sd_k z_k.  Weight
+ * matrices are used rounded to bfloat16, biases in FP32.  Parameters
+ * (KRT_MLP_PARAMS floats): W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64],
+ * b3[64], W4[8][64], b4[8]; norm[16] = (mu[8], sd[8]).  Domain of use:
+ * kappa in [3, 8], w in [1, 100], X in [1e-2, 1e6]. */
+#define KRT_MLP_PARAMS 9160
+
+/* Host arrays in, copied to the context (the packed inference form is rebuilt). */
+krt_status krt_mlp_set_params(krt_ctx* ctx, const float* params, const double norm[16]);
+/* Copies the current parameters and normalisation to host arrays (synchronises). */
+krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double norm[16]);
+/* Random initial weights (uniform, scaled by 1/sqrt(fan-in)), zero biases,
+ * from a SplitMix64 stream of `seed`; norm = (0, 1) until training sets it. */
+krt_status krt_mlp_init(krt_ctx* ctx, uint64_t seed);
+
+/* Gradient of the loss L = sum over the n samples and 8 outputs of
+ * (z - t)^2 / (8 n), t = (log10 integral - mu) / sd, with respect to the
+ * parameters (straight through the bfloat16 rounding), for inputs d_in [n][4]
+ * = (kappa, w, X, cos theta_B) and exact integrals d_integ [n][8] (device);
+ * d_grad [KRT_MLP_PARAMS] (device); *out_loss = L (synchronises). */
+krt_status krt_mlp_grad(krt_ctx* ctx, int64_t n, const double* d_in, const double* d_integ, float* d_grad,
+                        double* out_loss);
+
+typedef struct krt_train_config {
+    uint32_t struct_size;
+    int32_t epochs;        /* passes over the set                              */
+    int32_t batch;         /* samples per Adam step (multiple of 32)           */
+    int32_t set_norm;      /* 1: mu, sd from this set; 0: keep the current ones */
+    double lr_max;         /* peak Adam step                                   */
+    double lr_min;         /* final step (cosine decay after a linear warm-up) */
+    double warmup_frac;    /* fraction of the steps spent warming up           */
+    uint64_t seed;         /* per-epoch sample order                           */
+} krt_train_config;
+
+/* Trains the MLP on the GPU with Adam (beta 0.9, 0.999, eps 1e-8) on the set
+ * d_in [n][4], d_integ [n][8] (device).  n a power of two: samples are visited
+ * in a fresh affine order modulo n every epoch; otherwise in the stored order.
+ * *out_loss = the loss over the whole set after training (synchronises). */
+krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const double* d_integ,
+                         const krt_train_config* cfg, double* out_loss);
+
+/* Surrogate inference on bf16 MFMA: d_in [n][4] = (kappa, w, X, cos theta_B),
+ * d_out [n][8] integrals (device).  Inputs outside the domain are evaluated
+ * as they are (no fallback here). */
+krt_status krt_mlp_eval(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out);
 
 #ifdef __cplusplus
 }

@@ -60,6 +60,15 @@ struct krt_ctx {
     double* red_partial = nullptr;
     double* host_buf = nullptr;  // pinned, 16 doubles
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // nonthermal electrons: synchrotron-function table (built on first use)
+    double* syntab = nullptr;
+    // surrogate: FP32 master parameters, Adam moments, normalisation, packed form
+    float* mlp_P = nullptr;
+    float* mlp_m = nullptr;
+    float* mlp_v = nullptr;
+    double* mlp_norm = nullptr;
+    MlpPacked* mlp_packed = nullptr;
+    bool mlp_ready = false;
     std::string err;
 };
 
@@ -367,6 +376,126 @@ krt_status check_ready(krt_ctx* ctx, const krt_camera* cam) {
     return KRT_OK;
 }
 
+
+// Synchrotron-function table of the nonthermal module, built on first use.
+krt_status ensure_syntab(krt_ctx* ctx) {
+    if (ctx->syntab) return KRT_OK;
+    double* vals = nullptr;
+    double* tab = nullptr;
+    if (hipMalloc(&vals, (size_t)kSynPanels * kSynCoef * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tab, (size_t)kSynTab * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (vals) (void)hipFree(vals);
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate the synchrotron table");
+    }
+    const int nn = kSynPanels * kSynCoef;
+    hipLaunchKernelGGL(syn_table_nodes, dim3((nn + 127) / 128), dim3(128), 0, ctx->stream, vals);
+    hipLaunchKernelGGL(syn_table_coefs, dim3((kSynTab + 127) / 128), dim3(128), 0, ctx->stream, vals, tab);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(vals);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipFree(tab);
+        return hip_fail(ctx, e, "synchrotron table");
+    }
+    ctx->syntab = tab;
+    return KRT_OK;
+}
+
+krt_status ensure_mlp(krt_ctx* ctx) {
+    if (ctx->mlp_P) return KRT_OK;
+    if (hipMalloc(&ctx->mlp_P, kMlpParams * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ctx->mlp_m, kMlpParams * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ctx->mlp_v, kMlpParams * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ctx->mlp_norm, 16 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ctx->mlp_packed, sizeof(MlpPacked)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate the surrogate's parameters");
+    }
+    return KRT_OK;
+}
+
+krt_status mlp_repack(krt_ctx* ctx) {
+    hipLaunchKernelGGL(mlp_pack, dim3(1), dim3(256), 0, ctx->stream, ctx->mlp_P, ctx->mlp_norm, ctx->mlp_packed);
+    KRT_HIP(ctx, hipGetLastError());
+    ctx->mlp_ready = true;
+    return KRT_OK;
+}
+
+uint64_t splitmix_next(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One pass of the training kernel over samples [first, first + count) of the
+// prepared set, partials into gpart / lpart; returns the number of blocks.
+int mlp_pass(krt_ctx* ctx, const float* feat, const float* targ, int64_t n, int64_t first, int64_t count,
+             bool permute, uint64_t a, uint64_t c, float* gpart, double* lpart) {
+    MlpTrainArgs A;
+    A.P = ctx->mlp_P;
+    A.feat = feat;
+    A.targ = targ;
+    A.n = n;
+    A.first = first;
+    A.count = count;
+    A.perm_a = a;
+    A.perm_c = c;
+    A.permute = permute ? 1 : 0;
+    A.inv_norm = (float)(1.0 / (8.0 * (double)count));
+    A.gpart = gpart;
+    A.lpart = lpart;
+    const int blocks = (int)((count + kTrainTile - 1) / kTrainTile);
+    hipLaunchKernelGGL(mlp_train_tile, dim3(blocks), dim3(256), 0, ctx->stream, A);
+    return blocks;
+}
+
+struct MlpScratch {
+    float* feat = nullptr;
+    float* targ = nullptr;
+    float* gpart = nullptr;
+    double* lpart = nullptr;
+    double* loss = nullptr;
+    ~MlpScratch() {
+        if (feat) (void)hipFree(feat);
+        if (targ) (void)hipFree(targ);
+        if (gpart) (void)hipFree(gpart);
+        if (lpart) (void)hipFree(lpart);
+        if (loss) (void)hipFree(loss);
+    }
+};
+
+krt_status mlp_scratch(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t max_batch) {
+    const int64_t blocks = (max_batch + kTrainTile - 1) / kTrainTile;
+    if (hipMalloc(&S.feat, (size_t)n * 4 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&S.targ, (size_t)n * 8 * sizeof(float)) != hipSuccess ||
+        hipMalloc(&S.gpart, (size_t)blocks * kMlpParams * sizeof(float)) != hipSuccess ||
+        hipMalloc(&S.lpart, (size_t)blocks * sizeof(double)) != hipSuccess ||
+        hipMalloc(&S.loss, sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate training scratch");
+    }
+    return KRT_OK;
+}
+
+// Loss over the whole prepared set (stored order), summed on the device.
+krt_status mlp_set_loss(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t chunk, double* out_loss) {
+    double total = 0.0;
+    for (int64_t first = 0; first < n; first += chunk) {
+        const int64_t cnt = std::min(chunk, n - first);
+        const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, false, 0, 0, S.gpart, S.lpart);
+        hipLaunchKernelGGL(mlp_loss_sum, dim3(1), dim3(64), 0, ctx->stream, S.lpart, blocks, S.loss);
+        KRT_HIP(ctx, hipGetLastError());
+        double h = 0.0;
+        KRT_HIP(ctx, hipMemcpyAsync(&h, S.loss, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        total += h;
+    }
+    *out_loss = total / (8.0 * (double)n);
+    return KRT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -449,6 +578,12 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->chunk_flags) (void)hipFree(ctx->chunk_flags);
     if (ctx->red_partial) (void)hipFree(ctx->red_partial);
     if (ctx->btab) (void)hipFree(ctx->btab);
+    if (ctx->syntab) (void)hipFree(ctx->syntab);
+    if (ctx->mlp_P) (void)hipFree(ctx->mlp_P);
+    if (ctx->mlp_m) (void)hipFree(ctx->mlp_m);
+    if (ctx->mlp_v) (void)hipFree(ctx->mlp_v);
+    if (ctx->mlp_norm) (void)hipFree(ctx->mlp_norm);
+    if (ctx->mlp_packed) (void)hipFree(ctx->mlp_packed);
     if (ctx->host_buf) (void)hipHostFree(ctx->host_buf);
     for (int k = 0; k < 3; ++k)
         if (ctx->ev[k]) (void)hipEventDestroy(ctx->ev[k]);
@@ -915,6 +1050,189 @@ krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     hipLaunchKernelGGL(hook_mueller, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, ctx->stream, n, d_coef,
                        d_S, w, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+
+krt_status krt_kappa_integrals(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    krt_status st = ensure_syntab(ctx);
+    if (st != KRT_OK) return st;
+    hipLaunchKernelGGL(hook_kappa_integrals, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream,
+                       ctx->syntab, n, d_in, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+krt_status krt_mueller_general(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S, double w,
+                               double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_coef || !d_S || !d_out)) || !std::isfinite(w) || w < 0.0)
+        return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(hook_mueller_general, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, ctx->stream, n,
+                       d_coef, d_S, w, d_out);
+    KRT_HIP(ctx, hipGetLastError());
+    return KRT_OK;
+}
+
+krt_status krt_mlp_set_params(krt_ctx* ctx, const float* params, const double norm[16]) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!params || !norm) return fail(ctx, KRT_E_INVAL, "params and norm are required");
+    for (int k = 0; k < kMlpParams; ++k)
+        if (!std::isfinite(params[k])) return fail(ctx, KRT_E_INVAL, "non-finite parameter");
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(norm[k]) || (k >= 8 && !(norm[k] > 0.0)))
+            return fail(ctx, KRT_E_INVAL, "norm must be finite with positive sd");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    krt_status st = ensure_mlp(ctx);
+    if (st != KRT_OK) return st;
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->mlp_P, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->mlp_norm, norm, 16 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_m, 0, kMlpParams * sizeof(float), ctx->stream));
+    KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_v, 0, kMlpParams * sizeof(float), ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return mlp_repack(ctx);
+}
+
+krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double norm[16]) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!params || !norm) return fail(ctx, KRT_E_INVAL, "params and norm are required");
+    if (!ctx->mlp_ready) return fail(ctx, KRT_E_STATE, "no surrogate parameters set");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    KRT_HIP(ctx, hipMemcpyAsync(params, ctx->mlp_P, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+    KRT_HIP(ctx, hipMemcpyAsync(norm, ctx->mlp_norm, 16 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return KRT_OK;
+}
+
+krt_status krt_mlp_init(krt_ctx* ctx, uint64_t seed) {
+    if (!ctx) return KRT_E_INVAL;
+    std::vector<float> P(kMlpParams, 0.0f);
+    uint64_t s = seed;
+    auto fill = [&](int off, int rows, int fan_in) {
+        const double b = std::sqrt(3.0 / fan_in) * 1.4142135623730951;
+        for (int k = 0; k < rows * fan_in; ++k) {
+            const double u = (double)(splitmix_next(s) >> 11) * 0x1.0p-53;
+            P[off + k] = (float)((2.0 * u - 1.0) * b);
+        }
+    };
+    fill(kOffW1, kMlpH, kMlpIn);
+    fill(kOffW2, kMlpH, kMlpH);
+    fill(kOffW3, kMlpH, kMlpH);
+    fill(kOffW4, kMlpOut, kMlpH);
+    const double norm[16] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
+    return krt_mlp_set_params(ctx, P.data(), norm);
+}
+
+krt_status krt_mlp_grad(krt_ctx* ctx, int64_t n, const double* d_in, const double* d_integ, float* d_grad,
+                        double* out_loss) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 1 || n > (int64_t)1 << 24 || !d_in || !d_integ || !d_grad)
+        return fail(ctx, KRT_E_INVAL, "bad arguments (1 <= n <= 2^24)");
+    if (!ctx->mlp_ready) return fail(ctx, KRT_E_STATE, "no surrogate parameters set");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    MlpScratch S;
+    krt_status st = mlp_scratch(ctx, S, n, n);
+    if (st != KRT_OK) return st;
+    hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
+                       ctx->mlp_norm, S.feat, S.targ);
+    const int blocks = mlp_pass(ctx, S.feat, S.targ, n, 0, n, false, 0, 0, S.gpart, S.lpart);
+    MlpStepArgs G{};
+    G.gpart = S.gpart;
+    G.nparts = blocks;
+    G.grad = d_grad;
+    hipLaunchKernelGGL(mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, ctx->stream, G);
+    hipLaunchKernelGGL(mlp_loss_sum, dim3(1), dim3(64), 0, ctx->stream, S.lpart, blocks, S.loss);
+    KRT_HIP(ctx, hipGetLastError());
+    double h = 0.0;
+    KRT_HIP(ctx, hipMemcpyAsync(&h, S.loss, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (out_loss) *out_loss = h / (8.0 * (double)n);
+    return KRT_OK;
+}
+
+krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const double* d_integ,
+                         const krt_train_config* cfg, double* out_loss) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!cfg || cfg->struct_size != sizeof(krt_train_config)) return fail(ctx, KRT_E_INVAL, "bad train config");
+    if (n < 32 || n > (int64_t)1 << 24 || !d_in || !d_integ) return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (cfg->epochs < 1 || cfg->batch < 32 || cfg->batch % kTrainTile != 0 || cfg->batch > (1 << 20) ||
+        !(cfg->lr_max > 0.0) || !(cfg->lr_min >= 0.0) || !(cfg->warmup_frac >= 0.0 && cfg->warmup_frac < 1.0))
+        return fail(ctx, KRT_E_INVAL, "bad train config values");
+    if (!ctx->mlp_ready) return fail(ctx, KRT_E_STATE, "no surrogate parameters set (krt_mlp_init)");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    const int64_t batch = std::min<int64_t>(cfg->batch, n);
+    MlpScratch S;
+    krt_status st = mlp_scratch(ctx, S, n, batch);
+    if (st != KRT_OK) return st;
+    if (cfg->set_norm) {
+        hipLaunchKernelGGL(mlp_norm, dim3(8), dim3(256), 0, ctx->stream, n, d_integ, ctx->mlp_norm);
+        KRT_HIP(ctx, hipGetLastError());
+    }
+    hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
+                       ctx->mlp_norm, S.feat, S.targ);
+    KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_m, 0, kMlpParams * sizeof(float), ctx->stream));
+    KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_v, 0, kMlpParams * sizeof(float), ctx->stream));
+    const bool pow2 = (n & (n - 1)) == 0;
+    const int64_t steps_per_epoch = (n + batch - 1) / batch;
+    const int64_t total = steps_per_epoch * cfg->epochs;
+    const int64_t warm = (int64_t)(cfg->warmup_frac * (double)total);
+    uint64_t rs = cfg->seed;
+    int64_t step = 0;
+    const double b1 = 0.9, b2 = 0.999;
+    for (int ep = 0; ep < cfg->epochs; ++ep) {
+        const uint64_t a = pow2 ? (splitmix_next(rs) | 1ull) : 1ull;
+        const uint64_t c = pow2 ? splitmix_next(rs) : 0ull;
+        for (int64_t first = 0; first < n; first += batch) {
+            const int64_t cnt = std::min(batch, n - first);
+            const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, pow2, a, c, S.gpart, S.lpart);
+            ++step;
+            double lr;
+            if (step <= warm) lr = cfg->lr_max * (double)step / (double)warm;
+            else {
+                const double f = (double)(step - warm) / (double)std::max<int64_t>(1, total - warm);
+                lr = cfg->lr_min + 0.5 * (cfg->lr_max - cfg->lr_min) * (1.0 + std::cos(kPi * f));
+            }
+            MlpStepArgs G{};
+            G.P = ctx->mlp_P;
+            G.m = ctx->mlp_m;
+            G.v = ctx->mlp_v;
+            G.gpart = S.gpart;
+            G.nparts = blocks;
+            G.grad = nullptr;
+            G.lr = (float)lr;
+            G.beta1 = (float)b1;
+            G.beta2 = (float)b2;
+            G.eps = 1e-8f;
+            G.bc1 = (float)(1.0 - std::pow(b1, (double)step));
+            G.bc2 = (float)(1.0 - std::pow(b2, (double)step));
+            hipLaunchKernelGGL(mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, ctx->stream, G);
+        }
+        KRT_HIP(ctx, hipGetLastError());
+    }
+    st = mlp_repack(ctx);
+    if (st != KRT_OK) return st;
+    double loss = 0.0;
+    st = mlp_set_loss(ctx, S, n, batch, &loss);
+    if (st != KRT_OK) return st;
+    if (out_loss) *out_loss = loss;
+    return KRT_OK;
+}
+
+krt_status krt_mlp_eval(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out) {
+    if (!ctx) return KRT_E_INVAL;
+    if (n < 0 || (n > 0 && (!d_in || !d_out))) return fail(ctx, KRT_E_INVAL, "bad arguments");
+    if (!ctx->mlp_ready) return fail(ctx, KRT_E_STATE, "no surrogate parameters set");
+    if (n == 0) return KRT_OK;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(hook_mlp_eval, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                       ctx->mlp_packed, n, d_in, d_out);
     KRT_HIP(ctx, hipGetLastError());
     return KRT_OK;
 }

@@ -15,6 +15,8 @@
 
 #include "krt_device.hpp"
 #include "krt_f32.hpp"
+#include "krt_kappa.hpp"
+#include "krt_mlp.hpp"
 
 namespace krt {
 
@@ -1023,6 +1025,23 @@ __global__ void hook_mueller(int64_t n, const double* coef, const double* S, dou
     double s[4] = {S[k * 4], S[k * 4 + 1], S[k * 4 + 2], S[k * 4 + 3]};
     mueller_thermal(c[0], c[1], c[2], c[3], c[4], c[5], w, s);
     for (int q = 0; q < 4; ++q) out[k * 4 + q] = s[q];
+}
+
+__global__ void hook_mueller_general(int64_t n, const double* coef, const double* S, double w, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double* c = coef + k * 8;
+    double s[4] = {S[k * 4], S[k * 4 + 1], S[k * 4 + 2], S[k * 4 + 3]};
+    mueller_general(c[0], c[1], c[2], c[3], c[4], c[5], c[6], c[7], w, s);
+    for (int q = 0; q < 4; ++q) out[k * 4 + q] = s[q];
+}
+
+__global__ void hook_kappa_integrals(const double* syntab, int64_t n, const double* in, double* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double o[8];
+    kappa_integrals(syntab, in[k * 3], in[k * 3 + 1], in[k * 3 + 2], o);
+    for (int q = 0; q < 8; ++q) out[k * 8 + q] = o[q];
 }
 
 }  // namespace krt

@@ -77,6 +77,12 @@ class LaunchConfig(ctypes.Structure):
                 "path_cap": self.path_cap, "order": self.order}
 
 
+class TrainConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("set_norm", ctypes.c_int32), ("lr_max", ctypes.c_double), ("lr_min", ctypes.c_double),
+                ("warmup_frac", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("group", ctypes.c_int32),
                 ("freq_hz", ctypes.c_double), ("M_unit_g", ctypes.c_double),
@@ -112,7 +118,18 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.POINTER(Stats)]),
     "krt_autotune": (ctypes.c_int, [_P, ctypes.POINTER(Camera), ctypes.c_int32, ctypes.POINTER(Instance),
                                     ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(LaunchConfig)]),
+    "krt_kappa_integrals": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
+    "krt_mueller_general": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_double, _P]),
+    "krt_mlp_set_params": (ctypes.c_int, [_P, _P, _P]),
+    "krt_mlp_get_params": (ctypes.c_int, [_P, _P, _P]),
+    "krt_mlp_init": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "krt_mlp_grad": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "krt_mlp_train": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.POINTER(TrainConfig),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "krt_mlp_eval": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
 }
+
+MLP_PARAMS = 9160
 
 PRECISION_FP64 = 0
 PRECISION_FP32_TRANSFER = 1
@@ -358,4 +375,82 @@ class Context:
         out = torch.empty_like(S)
         self._stream()
         self._check(lib().krt_mueller_step(self.h, coef.shape[0], _ptr(coef), _ptr(S), float(w), _ptr(out)))
+        return out
+
+    # ---- nonthermal electrons and the learned surrogate ----
+    def kappa_integrals(self, inp):
+        """inp [n, 3] float64 device (kappa, w, X) -> [n, 8] integrals."""
+        inp = _dev(inp, self.device)
+        if inp.dtype != torch.float64 or inp.dim() != 2 or inp.shape[1] != 3:
+            raise ValueError("inputs must be float64 [n, 3]")
+        out = torch.empty((inp.shape[0], 8), dtype=torch.float64, device=self.device)
+        self._stream()
+        self._check(lib().krt_kappa_integrals(self.h, inp.shape[0], _ptr(inp), _ptr(out)))
+        return out
+
+    def mueller_general(self, coef, S, w):
+        coef, S = _dev(coef, self.device), _dev(S, self.device)
+        if coef.shape[1] != 8 or S.shape[1] != 4:
+            raise ValueError("coef [n, 8] and S [n, 4]")
+        out = torch.empty_like(S)
+        self._stream()
+        self._check(lib().krt_mueller_general(self.h, coef.shape[0], _ptr(coef), _ptr(S), float(w), _ptr(out)))
+        return out
+
+    def mlp_set_params(self, params, norm):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nm = np.ascontiguousarray(norm, dtype=np.float64)
+        if p.size != MLP_PARAMS or nm.size != 16:
+            raise ValueError(f"params must hold {MLP_PARAMS} floats and norm 16 doubles")
+        self._stream()
+        self._check(lib().krt_mlp_set_params(self.h, p.ctypes.data_as(_P), nm.ctypes.data_as(_P)))
+
+    def mlp_get_params(self):
+        import numpy as np
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        nm = np.empty(16, dtype=np.float64)
+        self._stream()
+        self._check(lib().krt_mlp_get_params(self.h, p.ctypes.data_as(_P), nm.ctypes.data_as(_P)))
+        return p, nm
+
+    def mlp_init(self, seed):
+        self._stream()
+        self._check(lib().krt_mlp_init(self.h, int(seed)))
+
+    def _set_check(self, inp, integ):
+        inp, integ = _dev(inp, self.device), _dev(integ, self.device)
+        if inp.dtype != torch.float64 or integ.dtype != torch.float64 or inp.dim() != 2 or inp.shape[1] != 4 \
+                or tuple(integ.shape) != (inp.shape[0], 8):
+            raise ValueError("inputs float64 [n, 4] and integrals float64 [n, 8]")
+        return inp, integ
+
+    def mlp_grad(self, inp, integ):
+        """Gradient of the standardised mean-square loss; returns (grad [9160] f32 tensor, loss)."""
+        inp, integ = self._set_check(inp, integ)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._stream()
+        self._check(lib().krt_mlp_grad(self.h, inp.shape[0], _ptr(inp), _ptr(integ), _ptr(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def mlp_train(self, inp, integ, epochs, batch=16384, lr_max=3e-3, lr_min=1e-6, warmup_frac=0.03, seed=1,
+                  set_norm=True):
+        inp, integ = self._set_check(inp, integ)
+        c = TrainConfig(ctypes.sizeof(TrainConfig), int(epochs), int(batch), 1 if set_norm else 0,
+                        float(lr_max), float(lr_min), float(warmup_frac), int(seed))
+        loss = ctypes.c_double()
+        self._stream()
+        self._check(lib().krt_mlp_train(self.h, inp.shape[0], _ptr(inp), _ptr(integ), ctypes.byref(c),
+                                        ctypes.byref(loss)))
+        return loss.value
+
+    def mlp_eval(self, inp):
+        """inp [n, 4] float64 (kappa, w, X, cos theta) -> [n, 8] integrals (bf16 MFMA)."""
+        inp = _dev(inp, self.device)
+        if inp.dtype != torch.float64 or inp.dim() != 2 or inp.shape[1] != 4:
+            raise ValueError("inputs must be float64 [n, 4]")
+        out = torch.empty((inp.shape[0], 8), dtype=torch.float64, device=self.device)
+        self._stream()
+        self._check(lib().krt_mlp_eval(self.h, inp.shape[0], _ptr(inp), _ptr(out)))
         return out

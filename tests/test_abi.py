@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(krt):
     missing = [s for s in declared_symbols() if not hasattr(L, s)]
     assert not missing
     assert set(declared_symbols()) == set(krt._SIGS)
-    assert krt.lib().krt_abi_version() == 3
+    assert krt.lib().krt_abi_version() == 4
 
 
 def test_struct_layouts_match_header(krt, tmp_path):
@@ -46,7 +46,8 @@ def test_struct_layouts_match_header(krt, tmp_path):
     import subprocess
     structs = {"krt_camera": krt.Camera, "krt_units": krt.Units, "krt_adaf": krt.Adaf,
                "krt_snapshot_desc": krt.SnapshotDesc, "krt_stats": krt.Stats,
-               "krt_launch_config": krt.LaunchConfig, "krt_instance": krt.Instance}
+               "krt_launch_config": krt.LaunchConfig, "krt_instance": krt.Instance,
+               "krt_train_config": krt.TrainConfig}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "krt.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
