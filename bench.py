@@ -166,13 +166,92 @@ def run_batch(args):
     print(json.dumps(line))
 
 
+def run_kappa(args):
+    """Snapshot image with kappa electrons (kappa = 5, w = Theta_e): the
+    surrogate's coefficients on bf16 MFMA inside the transfer kernel, the
+    exact integrator outside its domain.  With --kappa-compare N, an N x N
+    image is also traced with the exact integrator at every point (flux
+    difference and rays/s gain of the surrogate)."""
+    import torch
+    from paper_2302_02733_amd import krt, train_kappa
+    from paper_2302_02733_amd import workloads as W
+
+    n = 4096 if args.workload == "kappa4096" else 512
+    desc = W.snapshot_desc()
+    prims = torch.tensor(W.make_snapshot(desc, 7), device="cuda")
+    cam = W.snapshot_camera(n)
+    stokes = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
+    with krt.Context(0) as ctx:
+        meta = train_kappa.load(ctx)
+        ctx.set_units(W.UNITS)
+        ctx.set_model_snapshot(desc, prims)
+        ctx.set_electrons(krt.ELECTRONS_KAPPA_SURROGATE, 5.0)
+        for _ in range(args.warmup):
+            ctx.trace(cam, stokes=stokes)
+            print("warmup step done", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kms, steps, pts = [], [], [0, 0]
+        for k in range(args.steps):
+            out = ctx.trace(cam, stokes=stokes)
+            st = out["stats"]
+            kms.append(st["kernel_ms"][0] + st["kernel_ms"][1])
+            steps.append(st["total_steps"])
+            pts = [st["surrogate_points"], st["exact_points"]]
+            print(f"step {k} done: {kms[-1]:.1f} ms in the tracers", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        flux = ctx.reduce(stokes, cam)[0]
+        compare = None
+        if args.kappa_compare:
+            m = args.kappa_compare
+            c2 = W.snapshot_camera(m)
+            res = {}
+            for kind in (krt.ELECTRONS_KAPPA_SURROGATE, krt.ELECTRONS_KAPPA_EXACT):
+                ctx.set_electrons(kind, 5.0)
+                s2 = torch.empty((4, m, m), dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                o = ctx.trace(c2, stokes=s2)
+                torch.cuda.synchronize()
+                res[kind] = (time.perf_counter() - t1, ctx.reduce(s2, c2)[0], o["stats"])
+                print(f"compare {m}x{m} electrons {kind}: {res[kind][0]:.2f} s", file=sys.stderr, flush=True)
+            ts, fs, _ = res[krt.ELECTRONS_KAPPA_SURROGATE]
+            te, fe, se = res[krt.ELECTRONS_KAPPA_EXACT]
+            compare = {"pixels": m * m, "surrogate_rays_per_s": m * m / ts, "exact_rays_per_s": m * m / te,
+                       "gain": te / ts, "flux_rel_diff": [abs(fs[q] - fe[q]) / fe[0] for q in range(4)],
+                       "flux_exact_jy": fe}
+    npix = n * n
+    line = {
+        "metric": "polarized rays/s with kappa electrons (surrogate coefficients on bf16 MFMA)",
+        "value": args.steps * npix / dt, "unit": "rays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+bf16", "data": "synthetic",
+        "config": {"workload": args.workload, "pixels": npix, "kappa": 5.0,
+                   "model": "synthetic GRMHD-like snapshot 288x128x128 (a=0.94, 20 deg, 230 GHz)",
+                   "surrogate": "MLP 4-64-64-64-8, bf16 weights, trained on the GPU "
+                                f"({meta['epochs']} epochs x {meta['rounds']} rounds)",
+                   "parallelism": "single GPU"},
+        "tracer_ms": sum(kms) / len(kms),
+        "mean_steps_per_ray": sum(steps) / len(steps) / npix,
+        "surrogate_points": pts[0], "exact_points": pts[1],
+        "fallback_fraction": pts[1] / max(1, pts[0] + pts[1]),
+        "flux_jy": flux,
+        "surrogate_test_p99": meta["test_rel_err"]["p99"],
+        "compare_with_exact": compare,
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="adaf1024",
-                    choices=["adaf64", "adaf1024", "adaf4096", "snap48", "snap2048", "batch256"])
+                    choices=["adaf64", "adaf1024", "adaf4096", "snap48", "snap2048", "batch256", "kappa512",
+                             "kappa4096"])
     ap.add_argument("--autotune", action="store_true",
                     help="batch256: pick the launch configuration with the library's tuner first")
     ap.add_argument("--batch-plain", action="store_true",
@@ -182,6 +261,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="fp32: FP32 transfer operators with FP64 geodesics and FP64 transfer state "
                          "(and the FP32 copy of the snapshot)")
+    ap.add_argument("--kappa-compare", type=int, default=0,
+                    help="kappa workloads: also trace an N x N image with the exact integrator everywhere")
     ap.add_argument("--flop-probe", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
@@ -195,6 +276,9 @@ def main():
 
     if args.workload == "batch256":
         run_batch(args)
+        return
+    if args.workload.startswith("kappa"):
+        run_kappa(args)
         return
 
     import numpy as np

@@ -136,6 +136,11 @@ typedef struct {
     int64_t long_rays;       /* rays longer than the fast path's store        */
     double kernel_ms[2];     /* device time of the wave-synchronous tracer and
                                 of the long-ray tracer (HIP events)           */
+    int64_t surrogate_points; /* kappa electrons: points whose coefficients
+                                 came from the surrogate                      */
+    int64_t exact_points;    /* kappa electrons: points evaluated with the
+                                exact integrator (all of them in the exact
+                                mode; the out-of-domain fallback otherwise)   */
 } krt_stats;
 
 /* ---- lifecycle ---- */
@@ -324,6 +329,20 @@ krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const
  * (4 pi m_e c^2), rho_Q and rho_V with the thermal prefactors times R_Q, R_V.
  */
 
+/* Electron distribution of the traced images (krt_trace, krt_trace_steps):
+ * THERMAL (default; the thermal coefficients), KAPPA_EXACT (kappa electrons
+ * of index `kappa` > 2 with w = Theta_e of the model, coefficients from the
+ * exact integrator at every point) or KAPPA_SURROGATE (the same, coefficients
+ * from the MLP below on bf16 MFMA inside the transfer kernel, the exact
+ * integrator for points outside its domain and for rays finished by the
+ * long-ray kernel).  Kappa modes use FP64 transfer and the general Stokes
+ * update (krt_mueller_general); KAPPA_SURROGATE needs surrogate parameters
+ * (krt_mlp_set_params or krt_mlp_train).  Batched libraries stay thermal. */
+#define KRT_ELECTRONS_THERMAL 0
+#define KRT_ELECTRONS_KAPPA_EXACT 1
+#define KRT_ELECTRONS_KAPPA_SURROGATE 2
+krt_status krt_set_electrons(krt_ctx* ctx, int kind, double kappa);
+
 /* Exact integrator: d_in [n][3] = (kappa, w, X) with kappa > 0, w > 0, X > 0
  * (device, doubles); d_out [n][8] the integrals above (device).  Trapezoid rule
  * in ln(g - 1), synchrotron functions from a Chebyshev table built on first use
@@ -355,7 +374,9 @@ krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double norm[16]);
 krt_status krt_mlp_init(krt_ctx* ctx, uint64_t seed);
 
 /* Gradient of the loss L = sum over the n samples and 8 outputs of
- * (z - t)^2 / (8 n), t = (log10 integral - mu) / sd, with respect to the
+ * c_k (z_k - t_k)^2 / (8 n), t = (log10 integral - mu) / sd, c_k = sd_k^2 /
+ * mean(sd^2) (the mean square error of log10 of the integrals, up to a
+ * constant: relative errors weigh alike in every output), with respect to the
  * parameters (straight through the bfloat16 rounding), for inputs d_in [n][4]
  * = (kappa, w, X, cos theta_B) and exact integrals d_integ [n][8] (device);
  * d_grad [KRT_MLP_PARAMS] (device); *out_loss = L (synchronises). */

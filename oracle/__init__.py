@@ -52,6 +52,7 @@ class Model(ctypes.Structure):
         ("slab_thetae", ctypes.c_double), ("slab_B", ctypes.c_double),
         ("slab_bdir", ctypes.c_double * 3), ("slab_jextra", ctypes.c_double * 3),
         ("slab_coef", ctypes.c_double * 8),
+        ("electrons", ctypes.c_int32), ("kappa", ctypes.c_double),
     ]
 
 
@@ -153,6 +154,8 @@ def make_model(d):
         arr = getattr(m, name)
         for k in range(n):
             arr[k] = float(v[k])
+    m.electrons = int(d.get("electrons", 0))
+    m.kappa = float(d.get("kappa", 0.0))
     return m
 
 

@@ -11,7 +11,8 @@ not shared with it):
 with the weight matrices rounded to bfloat16 (round to nearest, ties to
 even) and the biases used as they are.  Parameter vector (9160 floats):
 W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[8][64], b4[8].
-Loss over n samples: L = sum (z - t)^2 / (8 n), t = (log10 I - mu) / sd.
+Loss over n samples: L = sum_k c_k (z_k - t_k)^2 / (8 n), t = (log10 I - mu) / sd,
+c_k = sd_k^2 / mean(sd^2).
 The backward pass below is the chain rule written out by hand; the tests
 check it against finite differences of the forward pass.
 """
@@ -86,9 +87,10 @@ def loss_and_grad(params, norm, inp, integ, rounded=True):
     t = (np.log10(np.asarray(integ, dtype=np.float64)) - norm[:8]) / norm[8:]
     z, (x, z1, h1, z2, h2, z3, h3) = forward_z(W, features(inp))
     n = x.shape[0]
+    c = norm[8:] ** 2 / np.mean(norm[8:] ** 2)
     d = z - t
-    loss = float(np.sum(d * d) / (8.0 * n))
-    dz = 2.0 * d / (8.0 * n)
+    loss = float(np.sum(c * d * d) / (8.0 * n))
+    dz = 2.0 * c * d / (8.0 * n)
 
     def dsilu(a):
         s = _sig(a)

@@ -71,6 +71,10 @@ typedef struct {
     double slab_bdir[3];                  /* field direction, Cartesian        */
     double slab_jextra[3];                /* extra invariant emissivity I,Q,V  */
     double slab_coef[8];  /* fixed: J_I J_Q J_V A_I A_Q A_V R_Q R_V (invariant) */
+    /* electrons of the ADAF / snapshot models: 0 thermal, 1 kappa of index
+     * `kappa` with width Theta_e (the nonthermal module) */
+    int32_t electrons;
+    double kappa;
 } or_model;
 
 /* Gridded snapshot description (modified Kerr-Schild grid). */

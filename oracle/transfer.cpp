@@ -254,7 +254,10 @@ static void radiative_update(const or_camera* cam, double L_cm, const or_model* 
         double bn = (bb > 0.0) ? std::sqrt(bb) : 0.0;
         double cth = (bn > 0.0) ? dot(g, K, p.b) / (bn * (-Ku)) : 0.0;
         double c[8];
-        thermal_coefficients(p.ne, p.thetae, p.B, nu, cth, c);
+        if (model->electrons == 1)
+            kappa_coefficients(OR_DIST_KAPPA, model->kappa, p.ne, p.thetae, p.B, nu, cth, c);
+        else
+            thermal_coefficients(p.ne, p.thetae, p.B, nu, cth, c);
         double fac = L_cm / cam->freq_hz;
         for (int k = 0; k < 3; ++k) coef[k] = fac * c[k] / (nu * nu);
         for (int k = 3; k < 8; ++k) coef[k] = fac * nu * c[k];

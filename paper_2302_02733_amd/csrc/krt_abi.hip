@@ -55,7 +55,7 @@ struct krt_ctx {
     size_t batch_dev_bytes = 0;
     void* batch_host = nullptr;
     size_t batch_host_bytes = 0;
-    // counters: [0] tile queue, [1] overflow count (unsigned); then 8 x u64
+    // counters: [0] tile queue, [1] overflow count (unsigned); then 10 x u64
     unsigned* work = nullptr;
     double* red_partial = nullptr;
     double* host_buf = nullptr;  // pinned, 16 doubles
@@ -69,12 +69,14 @@ struct krt_ctx {
     double* mlp_norm = nullptr;
     MlpPacked* mlp_packed = nullptr;
     bool mlp_ready = false;
+    int electrons = KRT_ELECTRONS_THERMAL;
+    double kappa = 5.0;
     std::string err;
 };
 
 namespace {
 
-constexpr int kWorkWords = 2 + 2 * 8;
+constexpr int kWorkWords = 2 + 2 * 10;
 constexpr int kRedBlocks = 1024;
 
 krt_status fail(krt_ctx* ctx, krt_status code, const std::string& msg) {
@@ -349,7 +351,7 @@ krt_status ensure_long(krt_ctx* ctx, int max_steps, size_t npix) {
 }
 
 krt_status fill_stats(krt_ctx* ctx, int64_t rays, krt_stats* s) {
-    KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, ctx->work + 2, 8 * sizeof(unsigned long long),
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, ctx->work + 2, 10 * sizeof(unsigned long long),
                                 hipMemcpyDeviceToHost, ctx->stream));
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const unsigned long long* c = reinterpret_cast<const unsigned long long*>(ctx->host_buf);
@@ -359,6 +361,8 @@ krt_status fill_stats(krt_ctx* ctx, int64_t rays, krt_stats* s) {
     for (int k = 0; k < 5; ++k) s->status_count[k] = (int64_t)c[1 + k];
     s->max_steps_seen = (int32_t)c[6];
     s->long_rays = (int64_t)c[7];
+    s->surrogate_points = (int64_t)c[8];
+    s->exact_points = (int64_t)c[9];
     float t0 = 0.0f, t1 = 0.0f;
     KRT_HIP(ctx, hipEventElapsedTime(&t0, ctx->ev[0], ctx->ev[1]));
     KRT_HIP(ctx, hipEventElapsedTime(&t1, ctx->ev[1], ctx->ev[2]));
@@ -432,8 +436,9 @@ uint64_t splitmix_next(uint64_t& s) {
 // One pass of the training kernel over samples [first, first + count) of the
 // prepared set, partials into gpart / lpart; returns the number of blocks.
 int mlp_pass(krt_ctx* ctx, const float* feat, const float* targ, int64_t n, int64_t first, int64_t count,
-             bool permute, uint64_t a, uint64_t c, float* gpart, double* lpart) {
+             bool permute, uint64_t a, uint64_t c, const float cw[8], float* gpart, double* lpart) {
     MlpTrainArgs A;
+    for (int k = 0; k < 8; ++k) A.cw[k] = cw[k];
     A.P = ctx->mlp_P;
     A.feat = feat;
     A.targ = targ;
@@ -449,6 +454,17 @@ int mlp_pass(krt_ctx* ctx, const float* feat, const float* targ, int64_t n, int6
     const int blocks = (int)((count + kTrainTile - 1) / kTrainTile);
     hipLaunchKernelGGL(mlp_train_tile, dim3(blocks), dim3(256), 0, ctx->stream, A);
     return blocks;
+}
+
+// Loss weights sd_k^2 / mean(sd^2) from the context's normalisation (synchronises).
+krt_status mlp_weights(krt_ctx* ctx, float cw[8]) {
+    double norm[16];
+    KRT_HIP(ctx, hipMemcpyAsync(norm, ctx->mlp_norm, 16 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    double m = 0.0;
+    for (int k = 0; k < 8; ++k) m += norm[8 + k] * norm[8 + k] / 8.0;
+    for (int k = 0; k < 8; ++k) cw[k] = (float)(norm[8 + k] * norm[8 + k] / m);
+    return KRT_OK;
 }
 
 struct MlpScratch {
@@ -480,11 +496,12 @@ krt_status mlp_scratch(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t max_batch
 }
 
 // Loss over the whole prepared set (stored order), summed on the device.
-krt_status mlp_set_loss(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t chunk, double* out_loss) {
+krt_status mlp_set_loss(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t chunk, const float cw[8],
+                        double* out_loss) {
     double total = 0.0;
     for (int64_t first = 0; first < n; first += chunk) {
         const int64_t cnt = std::min(chunk, n - first);
-        const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, false, 0, 0, S.gpart, S.lpart);
+        const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, false, 0, 0, cw, S.gpart, S.lpart);
         hipLaunchKernelGGL(mlp_loss_sum, dim3(1), dim3(64), 0, ctx->stream, S.lpart, blocks, S.loss);
         KRT_HIP(ctx, hipGetLastError());
         double h = 0.0;
@@ -658,11 +675,23 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     if (!d_stokes) return fail(ctx, KRT_E_INVAL, "d_stokes is NULL");
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     const size_t npix = (size_t)cam->nx * cam->ny;
-    const bool f32 = ctx->precision == KRT_PRECISION_FP32_TRANSFER;
-    if ((st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx)) != KRT_OK) return st;
+    const int el = ctx->electrons;
+    const bool f32 = el == KRT_ELECTRONS_THERMAL && ctx->precision == KRT_PRECISION_FP32_TRANSFER;
+    if (el != KRT_ELECTRONS_THERMAL) {
+        if ((st = ensure_syntab(ctx)) != KRT_OK) return st;
+        if (el == KRT_ELECTRONS_KAPPA_SURROGATE && !ctx->mlp_ready)
+            return fail(ctx, KRT_E_STATE, "kappa surrogate selected but no surrogate parameters set");
+    }
+    if (el == KRT_ELECTRONS_KAPPA_SURROGATE) st = ensure_pool<kModeKapMlp>(ctx);
+    else if (el == KRT_ELECTRONS_KAPPA_EXACT) st = ensure_pool<kModeKapExact>(ctx);
+    else st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx);
+    if (st != KRT_OK) return st;
     if ((st = ensure_chunks(ctx)) != KRT_OK) return st;
     if ((st = ensure_long(ctx, cam->max_steps, npix)) != KRT_OK) return st;
     TraceArgs A = base_args(ctx, cam);
+    A.kappa = ctx->kappa;
+    A.syntab = ctx->syntab;
+    A.mlp = ctx->mlp_packed;
     A.pool = ctx->pool;
     A.cap = ctx->pool_cap;
     A.chunk_pool = ctx->chunk_pool;
@@ -678,16 +707,24 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     A.nsteps = d_nsteps;
     KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
-    if (f32)
-        hipLaunchKernelGGL(trace_waves<kModeF32>, dim3(ctx->launch_blocks), dim3(256), 0, ctx->stream, A);
+    const dim3 grid(ctx->launch_blocks), lgrid(ctx->long_slots / 64);
+    if (el == KRT_ELECTRONS_KAPPA_SURROGATE)
+        hipLaunchKernelGGL(trace_waves<kModeKapMlp>, grid, dim3(256), 0, ctx->stream, A);
+    else if (el == KRT_ELECTRONS_KAPPA_EXACT)
+        hipLaunchKernelGGL(trace_waves<kModeKapExact>, grid, dim3(256), 0, ctx->stream, A);
+    else if (f32)
+        hipLaunchKernelGGL(trace_waves<kModeF32>, grid, dim3(256), 0, ctx->stream, A);
     else
-        hipLaunchKernelGGL(trace_waves<kModeF64>, dim3(ctx->launch_blocks), dim3(256), 0, ctx->stream, A);
+        hipLaunchKernelGGL(trace_waves<kModeF64>, grid, dim3(256), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
-    if (f32)
-        hipLaunchKernelGGL(trace_long<kModeF32>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+    // long rays of either kappa mode use the exact integrator
+    if (el != KRT_ELECTRONS_THERMAL)
+        hipLaunchKernelGGL(trace_long<kModeKapExact>, lgrid, dim3(64), 0, ctx->stream, A);
+    else if (f32)
+        hipLaunchKernelGGL(trace_long<kModeF32>, lgrid, dim3(64), 0, ctx->stream, A);
     else
-        hipLaunchKernelGGL(trace_long<kModeF64>, dim3(ctx->long_slots / 64), dim3(64), 0, ctx->stream, A);
+        hipLaunchKernelGGL(trace_long<kModeF64>, lgrid, dim3(64), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
     if (out_stats) return fill_stats(ctx, (int64_t)cam->nx * cam->ny, out_stats);
@@ -1055,6 +1092,17 @@ krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const
 }
 
 
+krt_status krt_set_electrons(krt_ctx* ctx, int kind, double kappa) {
+    if (!ctx) return KRT_E_INVAL;
+    if (kind != KRT_ELECTRONS_THERMAL && kind != KRT_ELECTRONS_KAPPA_EXACT && kind != KRT_ELECTRONS_KAPPA_SURROGATE)
+        return fail(ctx, KRT_E_INVAL, "unknown electron distribution");
+    if (kind != KRT_ELECTRONS_THERMAL && !(std::isfinite(kappa) && kappa > 2.0))
+        return fail(ctx, KRT_E_INVAL, "kappa must be finite and > 2");
+    ctx->electrons = kind;
+    if (kind != KRT_ELECTRONS_THERMAL) ctx->kappa = kappa;
+    return KRT_OK;
+}
+
 krt_status krt_kappa_integrals(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out) {
     if (!ctx) return KRT_E_INVAL;
     if (n < 0 || (n > 0 && (!d_in || !d_out))) return fail(ctx, KRT_E_INVAL, "bad arguments");
@@ -1140,9 +1188,11 @@ krt_status krt_mlp_grad(krt_ctx* ctx, int64_t n, const double* d_in, const doubl
     MlpScratch S;
     krt_status st = mlp_scratch(ctx, S, n, n);
     if (st != KRT_OK) return st;
+    float cw[8];
+    if ((st = mlp_weights(ctx, cw)) != KRT_OK) return st;
     hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
                        ctx->mlp_norm, S.feat, S.targ);
-    const int blocks = mlp_pass(ctx, S.feat, S.targ, n, 0, n, false, 0, 0, S.gpart, S.lpart);
+    const int blocks = mlp_pass(ctx, S.feat, S.targ, n, 0, n, false, 0, 0, cw, S.gpart, S.lpart);
     MlpStepArgs G{};
     G.gpart = S.gpart;
     G.nparts = blocks;
@@ -1175,6 +1225,8 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
         hipLaunchKernelGGL(mlp_norm, dim3(8), dim3(256), 0, ctx->stream, n, d_integ, ctx->mlp_norm);
         KRT_HIP(ctx, hipGetLastError());
     }
+    float cw[8];
+    if ((st = mlp_weights(ctx, cw)) != KRT_OK) return st;
     hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
                        ctx->mlp_norm, S.feat, S.targ);
     KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_m, 0, kMlpParams * sizeof(float), ctx->stream));
@@ -1191,7 +1243,7 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
         const uint64_t c = pow2 ? splitmix_next(rs) : 0ull;
         for (int64_t first = 0; first < n; first += batch) {
             const int64_t cnt = std::min(batch, n - first);
-            const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, pow2, a, c, S.gpart, S.lpart);
+            const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, pow2, a, c, cw, S.gpart, S.lpart);
             ++step;
             double lr;
             if (step <= warm) lr = cfg->lr_max * (double)step / (double)warm;
@@ -1219,7 +1271,7 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
     st = mlp_repack(ctx);
     if (st != KRT_OK) return st;
     double loss = 0.0;
-    st = mlp_set_loss(ctx, S, n, batch, &loss);
+    st = mlp_set_loss(ctx, S, n, batch, cw, &loss);
     if (st != KRT_OK) return st;
     if (out_loss) *out_loss = loss;
     return KRT_OK;

@@ -25,8 +25,14 @@ enum : uint8_t { kEscaped = 0, kCaptured = 1, kStepCap = 2, kNonFinite = 3, kAxi
 
 enum : int { kModelAdaf = 0, kModelSnapshot = 1 };
 
-// Kernel modes: FP64 transfer, geodesics only, FP32 transfer operators.
-enum : int { kModeF64 = 0, kModeGeo = 1, kModeF32 = 2 };
+// Kernel modes: FP64 transfer, geodesics only, FP32 transfer operators, and
+// FP64 transfer with kappa electrons (coefficients from the exact integrator
+// at every point, or from the MFMA surrogate with the exact integrator
+// outside its domain).
+enum : int { kModeF64 = 0, kModeGeo = 1, kModeF32 = 2, kModeKapExact = 3, kModeKapMlp = 4 };
+
+template <int kMode>
+constexpr bool kKappa = kMode == kModeKapExact || kMode == kModeKapMlp;
 
 struct TraceArgs {
     CameraDesc cam;
@@ -66,7 +72,11 @@ struct TraceArgs {
     uint8_t* status;    // [ny][nx] or null
     int32_t* nsteps;    // [ny][nx] or null
     double* end_state;  // geodesic-only mode: [ny][nx][8]
-    unsigned long long* counters;  // steps, status[5], max steps, long rays
+    unsigned long long* counters;  // steps, status[5], max steps, long rays, surrogate / exact points
+    // kappa electrons
+    double kappa;
+    const double* syntab;       // synchrotron-function table
+    const MlpPacked* mlp;       // packed surrogate
 };
 
 // ---------------------------------------------------------------------------
@@ -347,6 +357,105 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
     }
 }
 
+// Fluid-frame inputs of the kappa coefficients at a stored point: false
+// where the point has no plasma (the update leaves N unchanged).
+KRT_HD bool kappa_point(const TraceArgs& A, const double pt[8], double& ne, double& w, double& B, double& nu,
+                        double& cth) {
+    const double r = pt[0], th = pt[1], ph = pt[2];
+    const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
+    Metric g;
+    metric_eval(A.cam.a, A.cam.m, r, th, g);
+    Plasma p;
+    if (!plasma_at(A, r, th, ph, g, p)) return false;
+    double Kl[4];
+    lower(g, K, Kl);
+    const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
+    nu = A.cam.freq * (-Ku);
+    const double bb = dot(g, p.b, p.b);
+    cth = bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
+    ne = p.ne;
+    w = p.thetae;
+    B = p.B;
+    return true;
+}
+
+// transfer_point for kappa electrons: the coefficients come from the eight
+// integrals I_in when use_in, else from the exact integrator (counted in
+// n_exact); the update is the general constant-coefficient one.
+KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, bool first, XferState& st,
+                                 Coh& N, const double* I_in, bool use_in, unsigned& n_exact) {
+    const double r = pt[0], th = pt[1], ph = pt[2];
+    const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
+    const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
+    Metric g;
+    MetricD dr, dh;
+    metric_eval_d(A.cam.a, A.cam.m, r, th, g, dr, dh);
+    double Ac[16];
+    connection(g, dr, dh, K, Ac);
+    double Dnext = 0.0;
+    if (first) {
+        for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
+        for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+    } else {
+        Dnext = st.Dnext;
+        Coh F;
+        transport_rhs(Ac, st.Ns, F);
+        const double hh = 0.5 * Dnext;
+        for (int k = 0; k < 10; ++k) N.R[k] = st.H.R[k] + hh * F.R[k];
+        for (int k = 0; k < 6; ++k) N.I[k] = st.H.I[k] + hh * F.I[k];
+    }
+    Plasma p;
+    if (plasma_at(A, r, th, ph, g, p)) {
+        double Kl[4];
+        lower(g, K, Kl);
+        const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
+        const double nu = A.cam.freq * (-Ku);
+        const double bb = dot(g, p.b, p.b);
+        const double cth =
+            bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
+        double X, sth;
+        if (kappa_frame(p.ne, p.thetae, p.B, nu, cth, X, sth)) {
+            double I[8];
+            if (use_in) {
+                for (int k = 0; k < 8; ++k) I[k] = I_in[k];
+            } else {
+                kappa_integrals(A.syntab, A.kappa, p.thetae, X, I);
+                ++n_exact;
+            }
+            double c[8];
+            kappa_physical(I, p.ne, p.B, nu, cth, sth, c);
+            bool zero = true;
+            for (int k = 0; k < 8; ++k) zero = zero && c[k] == 0.0;
+            if (!zero) {
+                // invariant forms: J = (L / nu_obs) j / nu^2, A = (L / nu_obs) nu alpha
+                const double fa = A.fac0 * nu;
+                const double fj = A.fac0 / (nu * nu);
+                double e1[4], l1[4], e2[4], l2[4];
+                fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+                double S[4];
+                coh_project(N, l1, l2, S);
+                mueller_general(fj * c[0], fj * c[1], fj * c[2], fa * c[3], fa * c[4], fa * c[5], fa * c[6],
+                                fa * c[7], 0.5 * (Dn + Dnext), S);
+                coh_rebuild(N, S, e1, e2);
+            }
+        }
+    }
+    if (n > 0) {
+        Coh F;
+        transport_rhs(Ac, N, F);
+        const double hh = 0.5 * Dn;
+        for (int k = 0; k < 10; ++k) {
+            st.H.R[k] = N.R[k] + hh * F.R[k];
+            st.Ns.R[k] = N.R[k] + Dn * F.R[k];
+        }
+        for (int k = 0; k < 6; ++k) {
+            st.H.I[k] = N.I[k] + hh * F.I[k];
+            st.Ns.I[k] = N.I[k] + Dn * F.I[k];
+        }
+        st.Dnext = Dn;
+    }
+}
+
 // Mixed-precision version of transfer_point: the operators at the point in
 // FP32, the coherency matrix and the Heun state in FP64, every increment
 // formed in FP32 (scaled by 2^160) and added in FP64.  The radiative update
@@ -521,6 +630,19 @@ __device__ __forceinline__ const double* point_addr(const TraceArgs& A, const do
     return A.chunk_pool + (size_t)c * A.cap * 512 + ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * 8;
 }
 
+// Surrogate and exact-integrator point counts of a wave, added once per tile.
+__device__ __forceinline__ void kappa_account(const TraceArgs& A, unsigned n_mlp, unsigned n_exact) {
+    unsigned long long a = n_mlp, b = n_exact;
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&A.counters[8], a);
+        atomicAdd(&A.counters[9], b);
+    }
+}
+
 // Transfer phase of one tile (all lanes on the same point index, far end
 // first), output and accounting.  Rays that overflowed the store are queued
 // for the long-ray kernel (with their instance in batch mode).
@@ -550,18 +672,45 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
     Coh N;
     for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
     for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
+    unsigned n_mlp = 0, n_exact = 0;
     for (int m = nmax; m >= 0; --m) {
-        if (m <= n_end) {
+        if constexpr (kMode == kModeKapMlp) {
+            // surrogate inputs of this lane's point (in-domain points only),
+            // the network for the whole wave, then the update
+            float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            bool want = false;
+            if (m <= n_end) {
+                double pt[8];
+                load_point(point_addr(A, slot, wchunks, m, lane), pt);
+                double ne, w, B, nu, cth, X, sth;
+                if (kappa_point(A, pt, ne, w, B, nu, cth) && kappa_frame(ne, w, B, nu, cth, X, sth) &&
+                    mlp_in_domain(A.kappa, w, X)) {
+                    mlp_features(A.kappa, w, X, cth, f);
+                    want = true;
+                }
+            }
+            double I[8];
+            if (__ballot(want) != 0ull) mlp_wave(A.mlp, f, I);
+            if (m <= n_end) {
+                double pt[8];
+                load_point(point_addr(A, slot, wchunks, m, lane), pt);
+                n_mlp += want ? 1u : 0u;
+                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want, n_exact);
+            }
+        } else if (m <= n_end) {
             double pt[8];
             load_point(point_addr(A, slot, wchunks, m, lane), pt);
             TraceArgs L = A;
             launder_transfer(L);
             if constexpr (kMode == kModeF32)
                 transfer_point_f32(L, pt, m, m == n_end, xs, N);
+            else if constexpr (kMode == kModeKapExact)
+                transfer_point_kappa(A, pt, m, m == n_end, xs, N, nullptr, false, n_exact);
             else
                 transfer_point(L, pt, m, m == n_end, xs, N);
         }
     }
+    if constexpr (kKappa<kMode>) kappa_account(A, n_mlp, n_exact);
     if (xfer) {
         double S[4];
         TraceArgs L = A;
@@ -663,12 +812,19 @@ __device__ __forceinline__ void stage_table(TraceArgs& A, double* s_btab, float*
 // idle.
 // ---------------------------------------------------------------------------
 template <int kMode>
-__global__ __launch_bounds__(256, 2) void trace_waves(TraceArgs A) {
+__global__ __launch_bounds__(256, kKappa<kMode> ? 1 : 2) void trace_waves(TraceArgs A) {
     constexpr bool kGeoOnly = kMode == kModeGeo;
     constexpr int kTab = kBesPanels * 2 * kBesCoef;
     __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
     __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
+    __shared__ int4 s_mlp[kMode == kModeKapMlp ? sizeof(MlpPacked) / 16 : 1];
     stage_table<kMode>(A, s_btab, s_btab_f);
+    if constexpr (kMode == kModeKapMlp) {
+        const int4* src = reinterpret_cast<const int4*>(A.mlp);
+        for (int k = threadIdx.x; k < (int)(sizeof(MlpPacked) / 16); k += blockDim.x) s_mlp[k] = src[k];
+        __syncthreads();
+        A.mlp = reinterpret_cast<const MlpPacked*>(s_mlp);
+    }
     const int lane = threadIdx.x & 63;
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
@@ -858,14 +1014,18 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
         typename std::conditional<kMode == kModeF32, XferStateF, XferState>::type xs;
         Coh N;
+        unsigned n_exact = 0;
         for (int m = n_end; m >= 0; --m) {
             double pt[8];
             load_point(path + (size_t)m * 8, pt);
             if constexpr (kMode == kModeF32)
                 transfer_point_f32(R, pt, m, m == n_end, xs, N);
+            else if constexpr (kKappa<kMode>)
+                transfer_point_kappa(R, pt, m, m == n_end, xs, N, nullptr, false, n_exact);
             else
                 transfer_point(R, pt, m, m == n_end, xs, N);
         }
+        if constexpr (kKappa<kMode>) atomicAdd(&A.counters[9], (unsigned long long)n_exact);
         double S[4];
         camera_output(R, alpha, beta, N, S);
         write_pixel(R, pix, S, st, n);

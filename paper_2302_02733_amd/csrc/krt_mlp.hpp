@@ -2,6 +2,11 @@
 // SiLU activations that maps (kappa, w, X, cos theta) to the eight
 // dimensionless integrals (as standardised log10 values).
 //
+// Loss: the mean over samples and outputs of cw_k (z_k - t_k)^2 with
+// t = standardised log10 of the exact integrals and cw_k = sd_k^2 / mean(sd^2),
+// i.e. the mean square error of log10 I (relative error weighted alike in
+// every output) up to a constant.
+//
 // Definition (training and inference compute this function):
 //   features  x = ((kappa - 5.5)/2.5, log10 w - 1, (log10 X - 2)/4, cos theta)
 //   h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), h3 = silu(W3 h2 + b3),
@@ -86,6 +91,7 @@ struct MlpTrainArgs {
     uint64_t perm_a, perm_c;  // position -> sample: (a p + c) mod n (n a power of two), or identity
     int permute;
     float inv_norm;       // 1 / (8 * batch size) of the loss
+    float cw[8];          // loss weight of each output: sd_k^2 / mean(sd^2)
     float* gpart;         // [gridDim.x][kMlpParams]
     double* lpart;        // [gridDim.x] sums of squared errors
 };
@@ -159,8 +165,8 @@ __global__ __launch_bounds__(256) void mlp_train_tile(MlpTrainArgs A) {
         float z = sB4[o];
         for (int j = 0; j < kMlpH; ++j) z += sW4[o * kMlpH + j] * sH[2][j * kLd + s];
         const float d = (base + s < end) ? z - sT[s][o] : 0.0f;
-        lsum = (double)d * (double)d;
-        sY[o][s] = 2.0f * d * A.inv_norm;   // dL/dz
+        lsum = (double)A.cw[o] * (double)d * (double)d;
+        sY[o][s] = 2.0f * A.cw[o] * d * A.inv_norm;   // dL/dz
     }
     sL[t] = lsum;
     __syncthreads();

@@ -59,12 +59,14 @@ class Stats(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("rays", ctypes.c_int64),
                 ("total_steps", ctypes.c_int64), ("status_count", ctypes.c_int64 * 5),
                 ("max_steps_seen", ctypes.c_int32), ("long_rays", ctypes.c_int64),
-                ("kernel_ms", ctypes.c_double * 2)]
+                ("kernel_ms", ctypes.c_double * 2), ("surrogate_points", ctypes.c_int64),
+                ("exact_points", ctypes.c_int64)]
 
     def as_dict(self):
         return {"rays": self.rays, "total_steps": self.total_steps,
                 "status_count": list(self.status_count), "max_steps_seen": self.max_steps_seen,
-                "long_rays": self.long_rays, "kernel_ms": list(self.kernel_ms)}
+                "long_rays": self.long_rays, "kernel_ms": list(self.kernel_ms),
+                "surrogate_points": self.surrogate_points, "exact_points": self.exact_points}
 
 
 class LaunchConfig(ctypes.Structure):
@@ -118,6 +120,7 @@ _SIGS = {
                                        ctypes.c_int32, ctypes.POINTER(Stats)]),
     "krt_autotune": (ctypes.c_int, [_P, ctypes.POINTER(Camera), ctypes.c_int32, ctypes.POINTER(Instance),
                                     ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(LaunchConfig)]),
+    "krt_set_electrons": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double]),
     "krt_kappa_integrals": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "krt_mueller_general": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P, ctypes.c_double, _P]),
     "krt_mlp_set_params": (ctypes.c_int, [_P, _P, _P]),
@@ -130,6 +133,7 @@ _SIGS = {
 }
 
 MLP_PARAMS = 9160
+ELECTRONS_THERMAL, ELECTRONS_KAPPA_EXACT, ELECTRONS_KAPPA_SURROGATE = 0, 1, 2
 
 PRECISION_FP64 = 0
 PRECISION_FP32_TRANSFER = 1
@@ -378,6 +382,10 @@ class Context:
         return out
 
     # ---- nonthermal electrons and the learned surrogate ----
+    def set_electrons(self, kind, kappa=5.0):
+        """ELECTRONS_THERMAL, ELECTRONS_KAPPA_EXACT or ELECTRONS_KAPPA_SURROGATE."""
+        self._check(lib().krt_set_electrons(self.h, int(kind), float(kappa)))
+
     def kappa_integrals(self, inp):
         """inp [n, 3] float64 device (kappa, w, X) -> [n, 8] integrals."""
         inp = _dev(inp, self.device)

@@ -1,0 +1,154 @@
+"""Images with kappa electrons on the GPU.
+
+- exact-integrator mode against the oracle's kappa render (parity bar set by
+  the integrators' agreement, ~5e-10 per coefficient: 1e-8 on flux and p99);
+- the trained surrogate (weights shipped with the package, trained on the GPU
+  by the library's kernels) against the oracle's integrator on the seeded
+  test set (coefficient error <= 1% at the 99th percentile), and surrogate
+  images against exact-integrator images (total flux within 1e-3);
+- the surrogate's gain in rays/s over the exact integrator at every point.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2302_02733_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+KAPPA = 5.0
+
+
+def _log(msg):
+    print(f"[gpu-kappa-img] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def krt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_02733_amd import krt as k
+    return k
+
+
+def _parity(S, So, flux_tol, p99_tol):
+    imax = So[0].max()
+    fo = So[0].sum()
+    flux = [abs(S[s].sum() - So[s].sum()) / fo for s in range(4)]
+    p99 = [np.percentile(np.abs(S[s] - So[s]).ravel() / imax, 99) for s in range(4)]
+    return flux, p99
+
+
+def test_kappa_exact_image_matches_oracle(krt):
+    cam = W.adaf_camera(8, eps=0.05, fov=30.0)
+    model = dict(W.ADAF, electrons=1, kappa=KAPPA)
+    _log("oracle kappa render 8x8 (eps 0.05)")
+    So, sto, nso = oracle.render(cam, W.UNITS, model)
+    with krt.Context(0) as ctx:
+        ctx.set_units(W.UNITS)
+        ctx.set_model(W.ADAF)
+        ctx.set_electrons(krt.ELECTRONS_KAPPA_EXACT, KAPPA)
+        ns = torch.empty((8, 8), dtype=torch.int32, device=ctx.device)
+        out = ctx.trace(cam, nsteps=ns)
+        torch.cuda.synchronize()
+        st = out["stats"]
+        S = out["stokes"].cpu().numpy()
+        _log(f"stats {st}")
+        assert np.array_equal(out["status"].cpu().numpy(), sto)
+        assert np.array_equal(ns.cpu().numpy(), nso)
+        assert st["exact_points"] > 0 and st["surrogate_points"] == 0
+    flux, p99 = _parity(S, So, 1e-8, 1e-8)
+    _log(f"kappa exact vs oracle: flux {flux}, p99 {p99}")
+    assert max(flux) <= 1e-8 and max(p99) <= 1e-8
+    # kappa electrons change the image (the distribution is not the thermal one)
+    St, _, _ = oracle.render(cam, W.UNITS, W.ADAF)
+    assert abs(St[0].sum() / So[0].sum() - 1) > 1e-3
+
+
+@pytest.fixture(scope="module")
+def trained(krt):
+    from paper_2302_02733_amd import train_kappa
+    assert os.path.exists(train_kappa.WEIGHTS), "trained surrogate weights are missing"
+    return train_kappa
+
+
+def test_surrogate_accuracy_against_oracle(krt, trained):
+    inp = W.kappa_inputs(1 << 16, 17)[:2048]   # part of the held-out test set
+    ref = oracle.kappa_integrals(inp[:, :3].copy())
+    with krt.Context(0) as ctx:
+        meta = trained.load(ctx)
+        got = ctx.mlp_eval(torch.tensor(inp, device=ctx.device)).cpu().numpy()
+    rel = np.abs(got / ref - 1)
+    p99 = np.percentile(rel, 99, axis=0)
+    _log(f"surrogate vs oracle: p50 {np.median(rel, 0)}, p99 {p99}, max {rel.max(0)}")
+    _log(f"training: {meta['epochs']} epochs x {meta['rounds']} rounds, final loss {meta['final_loss']:.3e}")
+    assert p99.max() <= 0.01
+
+
+def _images(krt, trained, cam, model, prims=None, desc=None):
+    out = {}
+    with krt.Context(0) as ctx:
+        trained.load(ctx)
+        ctx.set_units(W.UNITS)
+        if prims is not None:
+            ctx.set_model_snapshot(desc, prims)
+        else:
+            ctx.set_model(model)
+        for kind in (krt.ELECTRONS_KAPPA_SURROGATE, krt.ELECTRONS_KAPPA_EXACT):
+            ctx.set_electrons(kind, KAPPA)
+            r = ctx.trace(cam)
+            torch.cuda.synchronize()
+            out[kind] = (r["stokes"].cpu().numpy(), r["stats"])
+    return out
+
+
+@pytest.mark.parametrize("case", ["adaf64", "snap48"])
+def test_surrogate_image_flux_within_1e3_of_exact(krt, trained, case):
+    w = W.workload(case)
+    prims = desc = None
+    if "snapshot" in w:
+        desc, seed = w["snapshot"]
+        prims = torch.tensor(W.make_snapshot(desc, seed), device="cuda")
+    imgs = _images(krt, trained, w["camera"], w["model"], prims, desc)
+    Sm, stm = imgs[krt.ELECTRONS_KAPPA_SURROGATE]
+    Se, ste = imgs[krt.ELECTRONS_KAPPA_EXACT]
+    flux = [abs(Sm[s].sum() - Se[s].sum()) / Se[0].sum() for s in range(4)]
+    p99 = [np.percentile(np.abs(Sm[s] - Se[s]).ravel() / Se[0].max(), 99) for s in range(4)]
+    frac = stm["exact_points"] / max(1, stm["exact_points"] + stm["surrogate_points"])
+    _log(f"{case}: surrogate vs exact flux {flux}, p99 {p99}; fallback fraction {frac:.4f}; "
+         f"kernel ms {stm['kernel_ms'][0]:.1f} vs {ste['kernel_ms'][0]:.1f}")
+    assert stm["surrogate_points"] > 0
+    assert max(flux) <= 1e-3
+    assert np.all(np.isfinite(Sm))
+
+
+def test_surrogate_gain_over_exact(krt, trained):
+    """Rays/s of the surrogate image over the exact-integrator image (64^2
+    snapshot at 20 degrees, kappa = 5)."""
+    w = W.workload("snap48")
+    desc, seed = w["snapshot"]
+    prims = torch.tensor(W.make_snapshot(desc, seed), device="cuda")
+    cam = W.snapshot_camera(64)
+    times = {}
+    with krt.Context(0) as ctx:
+        trained.load(ctx)
+        ctx.set_units(W.UNITS)
+        ctx.set_model_snapshot(desc, prims)
+        for kind in (krt.ELECTRONS_KAPPA_SURROGATE, krt.ELECTRONS_KAPPA_EXACT):
+            ctx.set_electrons(kind, KAPPA)
+            ctx.trace(cam)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                ctx.trace(cam, stats=False)
+            torch.cuda.synchronize()
+            times[kind] = (time.perf_counter() - t0) / 3
+    gain = times[krt.ELECTRONS_KAPPA_EXACT] / times[krt.ELECTRONS_KAPPA_SURROGATE]
+    _log(f"surrogate {times[krt.ELECTRONS_KAPPA_SURROGATE] * 1e3:.1f} ms, exact "
+         f"{times[krt.ELECTRONS_KAPPA_EXACT] * 1e3:.1f} ms per 64^2 image: gain {gain:.1f}x")
+    assert gain > 1.5

@@ -24,7 +24,7 @@ def _set(n, seed):
     inp = np.stack([r.uniform(3, 8, n), 10 ** r.uniform(0, 2, n), 10 ** r.uniform(-2, 6, n),
                     np.cos(r.uniform(0, np.pi, n))], 1)
     integ = 10 ** r.normal(-3, 2, (n, 8))
-    norm = np.concatenate([np.full(8, -3.0), np.full(8, 2.0)])
+    norm = np.concatenate([np.full(8, -3.0), np.linspace(0.5, 3.0, 8)])
     return inp, integ, norm
 
 
