@@ -357,12 +357,12 @@ krt_status krt_mueller_general(krt_ctx* ctx, int64_t n, const double* d_coef, co
                                double* d_out);
 
 /* Learned surrogate of the eight integrals: an MLP 4 -> 64 -> 64 -> 64 -> 8
- * (SiLU) on the features ((kappa - 5.5)/2.5, log10 w - 1, (log10 X - 2)/4,
+ * (SiLU) on the features ((kappa - 5.5)/2.5, log10(w)/2, (log10 X - 4)/6,
  * cos theta_B) whose outputs z give log10 I_k = mu_k + sd_k z_k.  Weight
  * matrices are used rounded to bfloat16, biases in FP32.  Parameters
  * (KRT_MLP_PARAMS floats): W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64],
  * b3[64], W4[8][64], b4[8]; norm[16] = (mu[8], sd[8]).  Domain of use:
- * kappa in [3, 8], w in [1, 100], X in [1e-2, 1e6]. */
+ * kappa in [3, 8], w in [1e-2, 1e2], X in [1e-2, 1e10]. */
 #define KRT_MLP_PARAMS 9160
 
 /* Host arrays in, copied to the context (the packed inference form is rebuilt). */
@@ -374,9 +374,7 @@ krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double norm[16]);
 krt_status krt_mlp_init(krt_ctx* ctx, uint64_t seed);
 
 /* Gradient of the loss L = sum over the n samples and 8 outputs of
- * c_k (z_k - t_k)^2 / (8 n), t = (log10 integral - mu) / sd, c_k = sd_k^2 /
- * mean(sd^2) (the mean square error of log10 of the integrals, up to a
- * constant: relative errors weigh alike in every output), with respect to the
+ * (z - t)^2 / (8 n), t = (log10 integral - mu) / sd, with respect to the
  * parameters (straight through the bfloat16 rounding), for inputs d_in [n][4]
  * = (kappa, w, X, cos theta_B) and exact integrals d_integ [n][8] (device);
  * d_grad [KRT_MLP_PARAMS] (device); *out_loss = L (synchronises). */

@@ -5,14 +5,13 @@ the GPU forward pass, the GPU backward pass and the GPU training kernels.
 
 The network, as the library defines it (restated here from that definition,
 not shared with it):
-    features x = ((kappa - 5.5)/2.5, log10 w - 1, (log10 X - 2)/4, cos theta)
+    features x = ((kappa - 5.5)/2.5, log10(w)/2, (log10 X - 4)/6, cos theta)
     h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), h3 = silu(W3 h2 + b3)
     z = W4 h3 + b4,       log10 I_k = mu_k + sd_k z_k,   silu(t) = t / (1 + e^-t)
 with the weight matrices rounded to bfloat16 (round to nearest, ties to
 even) and the biases used as they are.  Parameter vector (9160 floats):
 W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[8][64], b4[8].
-Loss over n samples: L = sum_k c_k (z_k - t_k)^2 / (8 n), t = (log10 I - mu) / sd,
-c_k = sd_k^2 / mean(sd^2).
+Loss over n samples: L = sum (z - t)^2 / (8 n), t = (log10 I - mu) / sd.
 The backward pass below is the chain rule written out by hand; the tests
 check it against finite differences of the forward pass.
 """
@@ -51,7 +50,7 @@ def pack(d):
 
 def features(inp):
     inp = np.asarray(inp, dtype=np.float64)
-    return np.stack([(inp[:, 0] - 5.5) / 2.5, np.log10(inp[:, 1]) - 1.0, (np.log10(inp[:, 2]) - 2.0) / 4.0,
+    return np.stack([(inp[:, 0] - 5.5) / 2.5, np.log10(inp[:, 1]) / 2.0, (np.log10(inp[:, 2]) - 4.0) / 6.0,
                      inp[:, 3]], axis=1)
 
 
@@ -87,10 +86,9 @@ def loss_and_grad(params, norm, inp, integ, rounded=True):
     t = (np.log10(np.asarray(integ, dtype=np.float64)) - norm[:8]) / norm[8:]
     z, (x, z1, h1, z2, h2, z3, h3) = forward_z(W, features(inp))
     n = x.shape[0]
-    c = norm[8:] ** 2 / np.mean(norm[8:] ** 2)
     d = z - t
-    loss = float(np.sum(c * d * d) / (8.0 * n))
-    dz = 2.0 * c * d / (8.0 * n)
+    loss = float(np.sum(d * d) / (8.0 * n))
+    dz = 2.0 * d / (8.0 * n)
 
     def dsilu(a):
         s = _sig(a)

@@ -436,9 +436,8 @@ uint64_t splitmix_next(uint64_t& s) {
 // One pass of the training kernel over samples [first, first + count) of the
 // prepared set, partials into gpart / lpart; returns the number of blocks.
 int mlp_pass(krt_ctx* ctx, const float* feat, const float* targ, int64_t n, int64_t first, int64_t count,
-             bool permute, uint64_t a, uint64_t c, const float cw[8], float* gpart, double* lpart) {
+             bool permute, uint64_t a, uint64_t c, float* gpart, double* lpart) {
     MlpTrainArgs A;
-    for (int k = 0; k < 8; ++k) A.cw[k] = cw[k];
     A.P = ctx->mlp_P;
     A.feat = feat;
     A.targ = targ;
@@ -454,17 +453,6 @@ int mlp_pass(krt_ctx* ctx, const float* feat, const float* targ, int64_t n, int6
     const int blocks = (int)((count + kTrainTile - 1) / kTrainTile);
     hipLaunchKernelGGL(mlp_train_tile, dim3(blocks), dim3(256), 0, ctx->stream, A);
     return blocks;
-}
-
-// Loss weights sd_k^2 / mean(sd^2) from the context's normalisation (synchronises).
-krt_status mlp_weights(krt_ctx* ctx, float cw[8]) {
-    double norm[16];
-    KRT_HIP(ctx, hipMemcpyAsync(norm, ctx->mlp_norm, 16 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    double m = 0.0;
-    for (int k = 0; k < 8; ++k) m += norm[8 + k] * norm[8 + k] / 8.0;
-    for (int k = 0; k < 8; ++k) cw[k] = (float)(norm[8 + k] * norm[8 + k] / m);
-    return KRT_OK;
 }
 
 struct MlpScratch {
@@ -496,12 +484,11 @@ krt_status mlp_scratch(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t max_batch
 }
 
 // Loss over the whole prepared set (stored order), summed on the device.
-krt_status mlp_set_loss(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t chunk, const float cw[8],
-                        double* out_loss) {
+krt_status mlp_set_loss(krt_ctx* ctx, MlpScratch& S, int64_t n, int64_t chunk, double* out_loss) {
     double total = 0.0;
     for (int64_t first = 0; first < n; first += chunk) {
         const int64_t cnt = std::min(chunk, n - first);
-        const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, false, 0, 0, cw, S.gpart, S.lpart);
+        const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, false, 0, 0, S.gpart, S.lpart);
         hipLaunchKernelGGL(mlp_loss_sum, dim3(1), dim3(64), 0, ctx->stream, S.lpart, blocks, S.loss);
         KRT_HIP(ctx, hipGetLastError());
         double h = 0.0;
@@ -1188,11 +1175,9 @@ krt_status krt_mlp_grad(krt_ctx* ctx, int64_t n, const double* d_in, const doubl
     MlpScratch S;
     krt_status st = mlp_scratch(ctx, S, n, n);
     if (st != KRT_OK) return st;
-    float cw[8];
-    if ((st = mlp_weights(ctx, cw)) != KRT_OK) return st;
     hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
                        ctx->mlp_norm, S.feat, S.targ);
-    const int blocks = mlp_pass(ctx, S.feat, S.targ, n, 0, n, false, 0, 0, cw, S.gpart, S.lpart);
+    const int blocks = mlp_pass(ctx, S.feat, S.targ, n, 0, n, false, 0, 0, S.gpart, S.lpart);
     MlpStepArgs G{};
     G.gpart = S.gpart;
     G.nparts = blocks;
@@ -1225,8 +1210,6 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
         hipLaunchKernelGGL(mlp_norm, dim3(8), dim3(256), 0, ctx->stream, n, d_integ, ctx->mlp_norm);
         KRT_HIP(ctx, hipGetLastError());
     }
-    float cw[8];
-    if ((st = mlp_weights(ctx, cw)) != KRT_OK) return st;
     hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
                        ctx->mlp_norm, S.feat, S.targ);
     KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_m, 0, kMlpParams * sizeof(float), ctx->stream));
@@ -1243,7 +1226,7 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
         const uint64_t c = pow2 ? splitmix_next(rs) : 0ull;
         for (int64_t first = 0; first < n; first += batch) {
             const int64_t cnt = std::min(batch, n - first);
-            const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, pow2, a, c, cw, S.gpart, S.lpart);
+            const int blocks = mlp_pass(ctx, S.feat, S.targ, n, first, cnt, pow2, a, c, S.gpart, S.lpart);
             ++step;
             double lr;
             if (step <= warm) lr = cfg->lr_max * (double)step / (double)warm;
@@ -1271,7 +1254,7 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
     st = mlp_repack(ctx);
     if (st != KRT_OK) return st;
     double loss = 0.0;
-    st = mlp_set_loss(ctx, S, n, batch, cw, &loss);
+    st = mlp_set_loss(ctx, S, n, batch, &loss);
     if (st != KRT_OK) return st;
     if (out_loss) *out_loss = loss;
     return KRT_OK;

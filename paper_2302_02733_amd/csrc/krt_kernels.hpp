@@ -359,13 +359,11 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
 
 // Fluid-frame inputs of the kappa coefficients at a stored point: false
 // where the point has no plasma (the update leaves N unchanged).
-KRT_HD bool kappa_point(const TraceArgs& A, const double pt[8], double& ne, double& w, double& B, double& nu,
-                        double& cth) {
+KRT_HD bool kappa_point(const TraceArgs& A, const double pt[8], Plasma& p, double& nu, double& cth) {
     const double r = pt[0], th = pt[1], ph = pt[2];
     const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
     Metric g;
     metric_eval(A.cam.a, A.cam.m, r, th, g);
-    Plasma p;
     if (!plasma_at(A, r, th, ph, g, p)) return false;
     double Kl[4];
     lower(g, K, Kl);
@@ -373,17 +371,16 @@ KRT_HD bool kappa_point(const TraceArgs& A, const double pt[8], double& ne, doub
     nu = A.cam.freq * (-Ku);
     const double bb = dot(g, p.b, p.b);
     cth = bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
-    ne = p.ne;
-    w = p.thetae;
-    B = p.B;
     return true;
 }
 
 // transfer_point for kappa electrons: the coefficients come from the eight
 // integrals I_in when use_in, else from the exact integrator (counted in
-// n_exact); the update is the general constant-coefficient one.
+// n_exact); the update is the general constant-coefficient one.  pre: the
+// plasma at the point when already evaluated (has_pre: it exists).
 KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, bool first, XferState& st,
-                                 Coh& N, const double* I_in, bool use_in, unsigned& n_exact) {
+                                 Coh& N, const double* I_in, bool use_in, unsigned& n_exact,
+                                 const Plasma* pre = nullptr, bool has_pre = false) {
     const double r = pt[0], th = pt[1], ph = pt[2];
     const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
     const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
@@ -405,7 +402,14 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
         for (int k = 0; k < 6; ++k) N.I[k] = st.H.I[k] + hh * F.I[k];
     }
     Plasma p;
-    if (plasma_at(A, r, th, ph, g, p)) {
+    bool have;
+    if (pre) {
+        have = has_pre;
+        if (have) p = *pre;
+    } else {
+        have = plasma_at(A, r, th, ph, g, p);
+    }
+    if (have) {
         double Kl[4];
         lower(g, K, Kl);
         const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
@@ -678,14 +682,16 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
             // surrogate inputs of this lane's point (in-domain points only),
             // the network for the whole wave, then the update
             float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            bool want = false;
+            bool want = false, has = false;
+            Plasma p;
             if (m <= n_end) {
                 double pt[8];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
-                double ne, w, B, nu, cth, X, sth;
-                if (kappa_point(A, pt, ne, w, B, nu, cth) && kappa_frame(ne, w, B, nu, cth, X, sth) &&
-                    mlp_in_domain(A.kappa, w, X)) {
-                    mlp_features(A.kappa, w, X, cth, f);
+                double nu, cth, X, sth;
+                has = kappa_point(A, pt, p, nu, cth);
+                if (has && kappa_frame(p.ne, p.thetae, p.B, nu, cth, X, sth) &&
+                    mlp_in_domain(A.kappa, p.thetae, X)) {
+                    mlp_features(A.kappa, p.thetae, X, cth, f);
                     want = true;
                 }
             }
@@ -695,7 +701,7 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
                 double pt[8];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 n_mlp += want ? 1u : 0u;
-                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want, n_exact);
+                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want, n_exact, &p, has);
             }
         } else if (m <= n_end) {
             double pt[8];
