@@ -177,7 +177,7 @@ def run_kappa(args):
     from paper_2302_02733_amd import workloads as W
 
     n = 4096 if args.workload == "kappa4096" else 512
-    desc = W.snapshot_desc()
+    desc = W.snapshot_desc(R_high=1.0)   # T_e = T_i in the disk: Theta_e 1-100 where it emits
     prims = torch.tensor(W.make_snapshot(desc, 7), device="cuda")
     cam = W.snapshot_camera(n)
     stokes = torch.empty((4, n, n), dtype=torch.float64, device="cuda")
@@ -229,7 +229,7 @@ def run_kappa(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+bf16", "data": "synthetic",
         "config": {"workload": args.workload, "pixels": npix, "kappa": 5.0,
-                   "model": "synthetic GRMHD-like snapshot 288x128x128 (a=0.94, 20 deg, 230 GHz)",
+                   "model": "synthetic GRMHD-like snapshot 288x128x128 (a=0.94, 20 deg, 230 GHz, R_high=1)",
                    "surrogate": "MLP 4-64-64-64-8, bf16 weights, trained on the GPU "
                                 f"({meta['epochs']} epochs x {meta['rounds']} rounds)",
                    "parallelism": "single GPU"},

@@ -357,24 +357,32 @@ krt_status krt_mueller_general(krt_ctx* ctx, int64_t n, const double* d_coef, co
                                double* d_out);
 
 /* Learned surrogate of the eight integrals: an MLP 4 -> 64 -> 64 -> 64 -> 8
- * (SiLU) on the features ((kappa - 5.5)/2.5, log10(w)/2, (log10 X - 4)/6,
- * cos theta_B) whose outputs z give log10 I_k = mu_k + sd_k z_k.  Weight
+ * (SiLU) on the features x = ((kappa - 5.5)/2.5, (log10 w - 0.75)/1.25,
+ * (log10 X - 2.5)/4.5, cos theta_B), whose outputs z give
+ * log10 I_k = sum_j c_kj m_j(x) + mu_k + sd_k z_k: a cubic baseline in
+ * (x0, x1, x2) (m_j: the 20 monomials of degree <= 3 in the order 1, x0, x1,
+ * x2, x0x0, x0x1, x0x2, x1x1, x1x2, x2x2, x0x0x0, x0x0x1, x0x0x2, x0x1x1,
+ * x0x1x2, x0x2x2, x1x1x1, x1x1x2, x1x2x2, x2x2x2), fitted by least squares
+ * on the training set, plus the network's standardised residual.  Weight
  * matrices are used rounded to bfloat16, biases in FP32.  Parameters
  * (KRT_MLP_PARAMS floats): W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64],
- * b3[64], W4[8][64], b4[8]; norm[16] = (mu[8], sd[8]).  Domain of use:
- * kappa in [3, 8], w in [1e-2, 1e2], X in [1e-2, 1e10]. */
+ * b3[64], W4[8][64], b4[8]; normalisation (KRT_MLP_NORM doubles): mu[8],
+ * sd[8], c[8][20].  Domain of use: kappa in [3, 8], w in [10^-0.5, 100],
+ * X in [1e-2, 1e7]. */
 #define KRT_MLP_PARAMS 9160
+#define KRT_MLP_NORM 176
 
 /* Host arrays in, copied to the context (the packed inference form is rebuilt). */
-krt_status krt_mlp_set_params(krt_ctx* ctx, const float* params, const double norm[16]);
+krt_status krt_mlp_set_params(krt_ctx* ctx, const float* params, const double* norm);
 /* Copies the current parameters and normalisation to host arrays (synchronises). */
-krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double norm[16]);
+krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double* norm);
 /* Random initial weights (uniform, scaled by 1/sqrt(fan-in)), zero biases,
- * from a SplitMix64 stream of `seed`; norm = (0, 1) until training sets it. */
+ * from a SplitMix64 stream of `seed`; normalisation mu = 0, sd = 1, c = 0
+ * until training sets it. */
 krt_status krt_mlp_init(krt_ctx* ctx, uint64_t seed);
 
 /* Gradient of the loss L = sum over the n samples and 8 outputs of
- * (z - t)^2 / (8 n), t = (log10 integral - mu) / sd, with respect to the
+ * (z - t)^2 / (8 n), t = (log10 integral - baseline - mu) / sd, with respect to the
  * parameters (straight through the bfloat16 rounding), for inputs d_in [n][4]
  * = (kappa, w, X, cos theta_B) and exact integrals d_integ [n][8] (device);
  * d_grad [KRT_MLP_PARAMS] (device); *out_loss = L (synchronises). */
@@ -385,7 +393,8 @@ typedef struct krt_train_config {
     uint32_t struct_size;
     int32_t epochs;        /* passes over the set                              */
     int32_t batch;         /* samples per Adam step (multiple of 32)           */
-    int32_t set_norm;      /* 1: mu, sd from this set; 0: keep the current ones */
+    int32_t set_norm;      /* 1: fit the baseline, mu and sd on this set;
+                              0: keep the current ones                         */
     double lr_max;         /* peak Adam step                                   */
     double lr_min;         /* final step (cosine decay after a linear warm-up) */
     double warmup_frac;    /* fraction of the steps spent warming up           */

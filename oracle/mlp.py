@@ -5,13 +5,16 @@ the GPU forward pass, the GPU backward pass and the GPU training kernels.
 
 The network, as the library defines it (restated here from that definition,
 not shared with it):
-    features x = ((kappa - 5.5)/2.5, log10(w)/2, (log10 X - 4)/6, cos theta)
+    features x = ((kappa - 5.5)/2.5, (log10 w - 0.75)/1.25, (log10 X - 2.5)/4.5, cos theta)
     h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), h3 = silu(W3 h2 + b3)
-    z = W4 h3 + b4,       log10 I_k = mu_k + sd_k z_k,   silu(t) = t / (1 + e^-t)
+    z = W4 h3 + b4,  log10 I_k = sum_j c_kj m_j(x) + mu_k + sd_k z_k,  silu(t) = t / (1 + e^-t)
+with m_j the 20 monomials of degree <= 3 in (x0, x1, x2) (order: 1, x0, x1,
+x2, then the degree-2 and degree-3 products with non-decreasing indices)
 with the weight matrices rounded to bfloat16 (round to nearest, ties to
 even) and the biases used as they are.  Parameter vector (9160 floats):
 W1[64][4], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[8][64], b4[8].
-Loss over n samples: L = sum (z - t)^2 / (8 n), t = (log10 I - mu) / sd.
+Normalisation vector (176): mu[8], sd[8], c[8][20].
+Loss over n samples: L = sum (z - t)^2 / (8 n), t = (log10 I - baseline - mu) / sd.
 The backward pass below is the chain rule written out by hand; the tests
 check it against finite differences of the forward pass.
 """
@@ -49,9 +52,21 @@ def pack(d):
 
 
 def features(inp):
+    """Feature rows, rounded to FP32 as the library forms them."""
     inp = np.asarray(inp, dtype=np.float64)
-    return np.stack([(inp[:, 0] - 5.5) / 2.5, np.log10(inp[:, 1]) / 2.0, (np.log10(inp[:, 2]) - 4.0) / 6.0,
-                     inp[:, 3]], axis=1)
+    f = np.stack([(inp[:, 0] - 5.5) / 2.5, (np.log10(inp[:, 1]) - 0.75) / 1.25, (np.log10(inp[:, 2]) - 2.5) / 4.5,
+                  inp[:, 3]], axis=1)
+    return f.astype(np.float32).astype(np.float64)
+
+
+def monomials(f):
+    """The 20 monomials of degree <= 3 in the first three features."""
+    import itertools
+    cols = [np.ones(f.shape[0])]
+    for deg in (1, 2, 3):
+        for c in itertools.combinations_with_replacement(range(3), deg):
+            cols.append(np.prod(f[:, list(c)], axis=1))
+    return np.stack(cols, axis=1)
 
 
 def _sig(z):
@@ -73,9 +88,11 @@ def forward_z(W, x):
 def predict_log10(params, norm, inp):
     """log10 of the eight integrals predicted for inputs [n, 4]."""
     W = unpack(params)
-    z, _ = forward_z(W, features(inp))
+    f = features(inp)
+    z, _ = forward_z(W, f)
     norm = np.asarray(norm, dtype=np.float64)
-    return norm[:8] + norm[8:] * z
+    base = monomials(f) @ norm[16:].reshape(8, 20).T
+    return base + norm[:8] + norm[8:16] * z
 
 
 def loss_and_grad(params, norm, inp, integ, rounded=True):
@@ -83,8 +100,10 @@ def loss_and_grad(params, norm, inp, integ, rounded=True):
     enter rounded; the gradient passes straight through the rounding)."""
     W = unpack(params, rounded=rounded)
     norm = np.asarray(norm, dtype=np.float64)
-    t = (np.log10(np.asarray(integ, dtype=np.float64)) - norm[:8]) / norm[8:]
-    z, (x, z1, h1, z2, h2, z3, h3) = forward_z(W, features(inp))
+    f = features(inp)
+    base = monomials(f) @ norm[16:].reshape(8, 20).T
+    t = (np.log10(np.asarray(integ, dtype=np.float64)) - base - norm[:8]) / norm[8:16]
+    z, (x, z1, h1, z2, h2, z3, h3) = forward_z(W, f)
     n = x.shape[0]
     d = z - t
     loss = float(np.sum(d * d) / (8.0 * n))

@@ -411,7 +411,7 @@ krt_status ensure_mlp(krt_ctx* ctx) {
     if (hipMalloc(&ctx->mlp_P, kMlpParams * sizeof(float)) != hipSuccess ||
         hipMalloc(&ctx->mlp_m, kMlpParams * sizeof(float)) != hipSuccess ||
         hipMalloc(&ctx->mlp_v, kMlpParams * sizeof(float)) != hipSuccess ||
-        hipMalloc(&ctx->mlp_norm, 16 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ctx->mlp_norm, kNormLen * sizeof(double)) != hipSuccess ||
         hipMalloc(&ctx->mlp_packed, sizeof(MlpPacked)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ctx, KRT_E_NOMEM, "cannot allocate the surrogate's parameters");
@@ -453,6 +453,66 @@ int mlp_pass(krt_ctx* ctx, const float* feat, const float* targ, int64_t n, int6
     const int blocks = (int)((count + kTrainTile - 1) / kTrainTile);
     hipLaunchKernelGGL(mlp_train_tile, dim3(blocks), dim3(256), 0, ctx->stream, A);
     return blocks;
+}
+
+// Least-squares cubic baseline of log10 I on the set (normal equations summed
+// on the device, solved here by Cholesky), and mu = 0, sd = the rms residual.
+krt_status mlp_fit_baseline(krt_ctx* ctx, int64_t n, const double* d_in, const double* d_integ) {
+    const int blocks = 256;
+    double* d_sums = nullptr;
+    if (hipMalloc(&d_sums, (size_t)blocks * kFitLen * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate fit sums");
+    }
+    hipLaunchKernelGGL(mlp_fit_sums, dim3(blocks), dim3(256), 0, ctx->stream, n, d_in, d_integ, d_sums);
+    std::vector<double> h((size_t)blocks * kFitLen);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_sums, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                            ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(d_sums);
+    if (e != hipSuccess) return hip_fail(ctx, e, "baseline fit");
+    std::vector<double> S(kFitLen, 0.0);
+    for (int b = 0; b < blocks; ++b)
+        for (int q = 0; q < kFitLen; ++q) S[q] += h[(size_t)b * kFitLen + q];
+    const int T = kPolyTerms;
+    // Cholesky of M^T M
+    std::vector<double> L(T * T, 0.0);
+    for (int i = 0; i < T; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double v = S[i * T + j];
+            for (int k = 0; k < j; ++k) v -= L[i * T + k] * L[j * T + k];
+            if (i == j) {
+                if (!(v > 0.0)) return fail(ctx, KRT_E_INVAL, "baseline fit is singular (too few samples?)");
+                L[i * T + i] = std::sqrt(v);
+            } else {
+                L[i * T + j] = v / L[j * T + j];
+            }
+        }
+    std::vector<double> norm(kNormLen, 0.0);
+    for (int o = 0; o < 8; ++o) {
+        double z[kPolyTerms], c[kPolyTerms];
+        for (int i = 0; i < T; ++i) {
+            double v = S[T * T + i * 8 + o];
+            for (int k = 0; k < i; ++k) v -= L[i * T + k] * z[k];
+            z[i] = v / L[i * T + i];
+        }
+        for (int i = T - 1; i >= 0; --i) {
+            double v = z[i];
+            for (int k = i + 1; k < T; ++k) v -= L[k * T + i] * c[k];
+            c[i] = v / L[i * T + i];
+        }
+        // residual sum of squares: y^T y - c^T M^T y
+        double rss = S[T * T + T * 8 + o];
+        for (int i = 0; i < T; ++i) rss -= c[i] * S[T * T + i * 8 + o];
+        norm[o] = 0.0;
+        norm[8 + o] = std::sqrt(std::max(rss / (double)n, 1e-30));
+        for (int i = 0; i < T; ++i) norm[16 + o * T + i] = c[i];
+    }
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->mlp_norm, norm.data(), kNormLen * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream));
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return KRT_OK;
 }
 
 struct MlpScratch {
@@ -1116,32 +1176,32 @@ krt_status krt_mueller_general(krt_ctx* ctx, int64_t n, const double* d_coef, co
     return KRT_OK;
 }
 
-krt_status krt_mlp_set_params(krt_ctx* ctx, const float* params, const double norm[16]) {
+krt_status krt_mlp_set_params(krt_ctx* ctx, const float* params, const double* norm) {
     if (!ctx) return KRT_E_INVAL;
     if (!params || !norm) return fail(ctx, KRT_E_INVAL, "params and norm are required");
     for (int k = 0; k < kMlpParams; ++k)
         if (!std::isfinite(params[k])) return fail(ctx, KRT_E_INVAL, "non-finite parameter");
-    for (int k = 0; k < 16; ++k)
-        if (!std::isfinite(norm[k]) || (k >= 8 && !(norm[k] > 0.0)))
+    for (int k = 0; k < kNormLen; ++k)
+        if (!std::isfinite(norm[k]) || (k >= 8 && k < 16 && !(norm[k] > 0.0)))
             return fail(ctx, KRT_E_INVAL, "norm must be finite with positive sd");
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     krt_status st = ensure_mlp(ctx);
     if (st != KRT_OK) return st;
     KRT_HIP(ctx, hipMemcpyAsync(ctx->mlp_P, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, ctx->stream));
-    KRT_HIP(ctx, hipMemcpyAsync(ctx->mlp_norm, norm, 16 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    KRT_HIP(ctx, hipMemcpyAsync(ctx->mlp_norm, norm, kNormLen * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_m, 0, kMlpParams * sizeof(float), ctx->stream));
     KRT_HIP(ctx, hipMemsetAsync(ctx->mlp_v, 0, kMlpParams * sizeof(float), ctx->stream));
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return mlp_repack(ctx);
 }
 
-krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double norm[16]) {
+krt_status krt_mlp_get_params(krt_ctx* ctx, float* params, double* norm) {
     if (!ctx) return KRT_E_INVAL;
     if (!params || !norm) return fail(ctx, KRT_E_INVAL, "params and norm are required");
     if (!ctx->mlp_ready) return fail(ctx, KRT_E_STATE, "no surrogate parameters set");
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     KRT_HIP(ctx, hipMemcpyAsync(params, ctx->mlp_P, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
-    KRT_HIP(ctx, hipMemcpyAsync(norm, ctx->mlp_norm, 16 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    KRT_HIP(ctx, hipMemcpyAsync(norm, ctx->mlp_norm, kNormLen * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return KRT_OK;
 }
@@ -1161,8 +1221,9 @@ krt_status krt_mlp_init(krt_ctx* ctx, uint64_t seed) {
     fill(kOffW2, kMlpH, kMlpH);
     fill(kOffW3, kMlpH, kMlpH);
     fill(kOffW4, kMlpOut, kMlpH);
-    const double norm[16] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1};
-    return krt_mlp_set_params(ctx, P.data(), norm);
+    std::vector<double> norm(kNormLen, 0.0);
+    for (int k = 8; k < 16; ++k) norm[k] = 1.0;
+    return krt_mlp_set_params(ctx, P.data(), norm.data());
 }
 
 krt_status krt_mlp_grad(krt_ctx* ctx, int64_t n, const double* d_in, const double* d_integ, float* d_grad,
@@ -1207,8 +1268,8 @@ krt_status krt_mlp_train(krt_ctx* ctx, int64_t n, const double* d_in, const doub
     krt_status st = mlp_scratch(ctx, S, n, batch);
     if (st != KRT_OK) return st;
     if (cfg->set_norm) {
-        hipLaunchKernelGGL(mlp_norm, dim3(8), dim3(256), 0, ctx->stream, n, d_integ, ctx->mlp_norm);
-        KRT_HIP(ctx, hipGetLastError());
+        st = mlp_fit_baseline(ctx, n, d_in, d_integ);
+        if (st != KRT_OK) return st;
     }
     hipLaunchKernelGGL(mlp_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, n, d_in, d_integ,
                        ctx->mlp_norm, S.feat, S.targ);

@@ -2,16 +2,21 @@
 // SiLU activations that maps (kappa, w, X, cos theta) to the eight
 // dimensionless integrals (as standardised log10 values).
 //
-// Loss: the mean over samples and outputs of (z_k - t_k)^2 with t the
-// standardised log10 of the exact integrals.
-//
 // Definition (training and inference compute this function):
-//   features  x = ((kappa - 5.5)/2.5, log10(w)/2, (log10 X - 4)/6, cos theta)
+//   features  x = ((kappa - 5.5)/2.5, (log10 w - 0.75)/1.25, (log10 X - 2.5)/4.5, cos theta)
 //   h1 = silu(W1 x + b1), h2 = silu(W2 h1 + b2), h3 = silu(W3 h2 + b3),
-//   z = W4 h3 + b4,  log10 I_k = mu_k + sd_k z_k,  silu(t) = t / (1 + e^-t),
+//   z = W4 h3 + b4,
+//   log10 I_k = sum_j c_kj m_j(x) + mu_k + sd_k z_k,  silu(t) = t / (1 + e^-t),
 // with every weight matrix rounded to bfloat16 (nearest even) and FP32
-// biases.  Domain: kappa in [3, 8], w in [1e-2, 1e2], X in [1e-2, 1e10]; outside
-// it the exact integrator is used.
+// biases; m_j are the 20 monomials of degree <= 3 in (x0, x1, x2), in the
+// order 1, x0, x1, x2, x0x0, x0x1, x0x2, x1x1, x1x2, x2x2, x0x0x0, x0x0x1,
+// x0x0x2, x0x1x1, x0x1x2, x0x2x2, x1x1x1, x1x1x2, x1x2x2, x2x2x2.  The cubic
+// baseline c is the least-squares fit of log10 I on the training set (it
+// takes out the integrals' many-decade trends), mu and sd the mean and
+// spread of what it leaves, which the network learns.  Loss: the mean over
+// samples and outputs of (z_k - t_k)^2, t = (log10 I - baseline - mu) / sd.
+// Domain: kappa in [3, 8], w in [10^-0.5, 10^2], X in [1e-2, 1e7]; outside it
+// the exact integrator is used.
 //
 // Training (FP32 vector ALU): per block 32 samples, forward and backward
 // through LDS-resident activations, per-block gradient partials, then one
@@ -41,7 +46,9 @@ constexpr int kOffW4 = kOffB3 + kMlpH;              // [8][64]
 constexpr int kOffB4 = kOffW4 + kMlpOut * kMlpH;
 constexpr int kMlpParams = kOffB4 + kMlpOut;        // 9160
 
-constexpr double kKapMin = 3.0, kKapMax = 8.0, kWMin = 1e-2, kWMax = 1e2, kXMin = 1e-2, kXMax = 1e10;
+constexpr double kKapMin = 3.0, kKapMax = 8.0, kWMin = 0.31622776601683794, kWMax = 1e2, kXMin = 1e-2, kXMax = 1e7;
+constexpr int kPolyTerms = 20;
+constexpr int kNormLen = 16 + 8 * kPolyTerms;   // mu[8], sd[8], c[8][20]
 
 KRT_HD bool mlp_in_domain(double kap, double w, double X) {
     return kap >= kKapMin && kap <= kKapMax && w >= kWMin && w <= kWMax && X >= kXMin && X <= kXMax;
@@ -49,9 +56,19 @@ KRT_HD bool mlp_in_domain(double kap, double w, double X) {
 
 KRT_HD void mlp_features(double kap, double w, double X, double cth, float f[4]) {
     f[0] = (float)((kap - 5.5) * 0.4);
-    f[1] = (float)(log10(w) * 0.5);
-    f[2] = (float)((log10(X) - 4.0) * (1.0 / 6.0));
+    f[1] = (float)((log10(w) - 0.75) * 0.8);
+    f[2] = (float)((log10(X) - 2.5) * (1.0 / 4.5));
     f[3] = (float)cth;
+}
+
+// The 20 monomials of degree <= 3 in (x0, x1, x2), in the documented order.
+template <class T>
+KRT_HD void mlp_monomials(T a, T b, T c, T m[kPolyTerms]) {
+    m[0] = T(1);
+    m[1] = a; m[2] = b; m[3] = c;
+    m[4] = a * a; m[5] = a * b; m[6] = a * c; m[7] = b * b; m[8] = b * c; m[9] = c * c;
+    m[10] = a * a * a; m[11] = a * a * b; m[12] = a * a * c; m[13] = a * b * b; m[14] = a * b * c;
+    m[15] = a * c * c; m[16] = b * b * b; m[17] = b * b * c; m[18] = b * c * c; m[19] = c * c * c;
 }
 
 // Round to bfloat16, nearest even (finite inputs), returned as float.
@@ -279,34 +296,63 @@ __global__ void mlp_prepare(int64_t n, const double* in, const double* integ, co
                             float* targ) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    mlp_features(in[k * 4], in[k * 4 + 1], in[k * 4 + 2], in[k * 4 + 3], feat + k * 4);
-    for (int o = 0; o < 8; ++o) targ[k * 8 + o] = (float)((log10(integ[k * 8 + o]) - norm[o]) / norm[8 + o]);
+    float* f = feat + k * 4;
+    mlp_features(in[k * 4], in[k * 4 + 1], in[k * 4 + 2], in[k * 4 + 3], f);
+    double m[kPolyTerms];
+    mlp_monomials<double>(f[0], f[1], f[2], m);
+    for (int o = 0; o < 8; ++o) {
+        double base = 0.0;
+        for (int j = 0; j < kPolyTerms; ++j) base += norm[16 + o * kPolyTerms + j] * m[j];
+        targ[k * 8 + o] = (float)((log10(integ[k * 8 + o]) - base - norm[o]) / norm[8 + o]);
+    }
 }
 
-// Mean and standard deviation of log10 of each integral (one block per output).
-__global__ void mlp_norm(int64_t n, const double* integ, double* norm) {
-    __shared__ double s1[256], s2[256];
-    const int o = blockIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int64_t k = threadIdx.x; k < n; k += 256) {
-        const double y = log10(integ[k * 8 + o]);
-        a += y;
-        b += y * y;
-    }
-    s1[threadIdx.x] = a;
-    s2[threadIdx.x] = b;
-    __syncthreads();
-    for (int st = 128; st >= 1; st >>= 1) {
-        if ((int)threadIdx.x < st) {
-            s1[threadIdx.x] += s1[threadIdx.x + st];
-            s2[threadIdx.x] += s2[threadIdx.x + st];
+// Sums for the least-squares baseline, per block: M^T M (20 x 20), M^T y
+// (20 x 8) and y^T y (8) over the block's samples, y = log10 of the
+// integrals, M the monomials of the FP32 features (out: [gridDim.x][628]).
+constexpr int kFitLen = kPolyTerms * kPolyTerms + kPolyTerms * 8 + 8;
+
+__global__ __launch_bounds__(256) void mlp_fit_sums(int64_t n, const double* in, const double* integ,
+                                                   double* out) {
+    __shared__ double sM[256][kPolyTerms + 1];
+    __shared__ double sY[256][9];
+    const int t = threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};   // entries q = t + 256 r of the sums
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        const int64_t k = base + t;
+        if (k < n) {
+            float f[4];
+            mlp_features(in[k * 4], in[k * 4 + 1], in[k * 4 + 2], in[k * 4 + 3], f);
+            double m[kPolyTerms];
+            mlp_monomials<double>(f[0], f[1], f[2], m);
+            for (int j = 0; j < kPolyTerms; ++j) sM[t][j] = m[j];
+            for (int o = 0; o < 8; ++o) sY[t][o] = log10(integ[k * 8 + o]);
+        } else {
+            for (int j = 0; j < kPolyTerms; ++j) sM[t][j] = 0.0;
+            for (int o = 0; o < 8; ++o) sY[t][o] = 0.0;
+        }
+        __syncthreads();
+        for (int r = 0; r < 3; ++r) {
+            const int q = t + 256 * r;
+            if (q >= kFitLen) break;
+            double sum = 0.0;
+            if (q < kPolyTerms * kPolyTerms) {
+                const int i = q / kPolyTerms, j = q % kPolyTerms;
+                for (int s = 0; s < 256; ++s) sum += sM[s][i] * sM[s][j];
+            } else if (q < kPolyTerms * kPolyTerms + kPolyTerms * 8) {
+                const int i = (q - kPolyTerms * kPolyTerms) / 8, o = (q - kPolyTerms * kPolyTerms) % 8;
+                for (int s = 0; s < 256; ++s) sum += sM[s][i] * sY[s][o];
+            } else {
+                const int o = q - kPolyTerms * kPolyTerms - kPolyTerms * 8;
+                for (int s = 0; s < 256; ++s) sum += sY[s][o] * sY[s][o];
+            }
+            acc[r] += sum;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double mu = s1[0] / n;
-        norm[o] = mu;
-        norm[8 + o] = sqrt(fmax(s2[0] / n - mu * mu, 1e-30));
+    for (int r = 0; r < 3; ++r) {
+        const int q = t + 256 * r;
+        if (q < kFitLen) out[(size_t)blockIdx.x * kFitLen + q] = acc[r];
     }
 }
 
@@ -324,6 +370,7 @@ struct MlpPacked {
     bf16x8 frag[kFrags][64];
     float b1[64], b2[64], b3[64], b4[8];
     float mu[8], sd[8];
+    float poly[8][kPolyTerms];
 };
 
 // Hidden unit fed to B-operand position (K step ks, lane half hf, element e):
@@ -368,6 +415,7 @@ __global__ void mlp_pack(const float* P, const double* norm, MlpPacked* out) {
         out->mu[t] = (float)norm[t];
         out->sd[t] = (float)norm[8 + t];
     }
+    for (int k = t; k < 8 * kPolyTerms; k += 256) out->poly[k / kPolyTerms][k % kPolyTerms] = (float)norm[16 + k];
 }
 
 __device__ __forceinline__ float silu_fast(float z) {
@@ -470,7 +518,13 @@ __device__ __forceinline__ void mlp_wave(const MlpPacked* __restrict__ W, const 
         z[4 * hf + v] = own;
         z[4 * (1 - hf) + v] = partner;
     }
-    for (int o = 0; o < 8; ++o) out[o] = exp10((double)(W->mu[o] + W->sd[o] * z[o]));
+    float m[kPolyTerms];
+    mlp_monomials<float>(f[0], f[1], f[2], m);
+    for (int o = 0; o < 8; ++o) {
+        float base = 0.0f;
+        for (int j = 0; j < kPolyTerms; ++j) base += W->poly[o][j] * m[j];
+        out[o] = exp10((double)(base + W->mu[o] + W->sd[o] * z[o]));
+    }
 }
 
 // Test hook / batch evaluation: in [n][4] (kappa, w, X, cos theta) -> out [n][8].

@@ -133,6 +133,7 @@ _SIGS = {
 }
 
 MLP_PARAMS = 9160
+MLP_NORM = 176
 ELECTRONS_THERMAL, ELECTRONS_KAPPA_EXACT, ELECTRONS_KAPPA_SURROGATE = 0, 1, 2
 
 PRECISION_FP64 = 0
@@ -409,15 +410,15 @@ class Context:
         import numpy as np
         p = np.ascontiguousarray(params, dtype=np.float32)
         nm = np.ascontiguousarray(norm, dtype=np.float64)
-        if p.size != MLP_PARAMS or nm.size != 16:
-            raise ValueError(f"params must hold {MLP_PARAMS} floats and norm 16 doubles")
+        if p.size != MLP_PARAMS or nm.size != MLP_NORM:
+            raise ValueError(f"params must hold {MLP_PARAMS} floats and norm {MLP_NORM} doubles")
         self._stream()
         self._check(lib().krt_mlp_set_params(self.h, p.ctypes.data_as(_P), nm.ctypes.data_as(_P)))
 
     def mlp_get_params(self):
         import numpy as np
         p = np.empty(MLP_PARAMS, dtype=np.float32)
-        nm = np.empty(16, dtype=np.float64)
+        nm = np.empty(MLP_NORM, dtype=np.float64)
         self._stream()
         self._check(lib().krt_mlp_get_params(self.h, p.ctypes.data_as(_P), nm.ctypes.data_as(_P)))
         return p, nm

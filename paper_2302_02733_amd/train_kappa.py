@@ -8,7 +8,7 @@ inference against the exact integrator on a separate seeded test set.
     python -m paper_2302_02733_amd.train_kappa [--epochs E] [--batch B] [--out PATH]
 
 Training set: 2^20 seeded inputs (seed 13); test set: 2^16 (seed 17); the
-box: kappa in [3, 8], w in [1e-2, 1e2], X in [1e-2, 1e10], theta_B in [0, pi].
+box: kappa in [3, 8], w in [10^-0.5, 100], X in [1e-2, 1e7], theta_B in [0, pi].
 """
 import argparse
 import json

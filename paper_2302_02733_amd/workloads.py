@@ -198,12 +198,12 @@ def batch_library(n_inst=256, seed=11, resolutions=(128, 256, 512, 1024)):
 
 def kappa_inputs(n, seed):
     """Seeded inputs of the kappa-coefficient surrogate: rows (kappa, w, X,
-    cos theta_B) with kappa ~ U[3, 8], log10 w ~ U[-2, 2], log10 X ~ U[-2, 10],
+    cos theta_B) with kappa ~ U[3, 8], log10 w ~ U[-0.5, 2], log10 X ~ U[-2, 7],
     theta_B ~ U[0, pi] (the box the network covers)."""
     import numpy as np
     r = np.random.Generator(np.random.PCG64(seed))
     kap = r.uniform(3.0, 8.0, n)
-    w = 10.0 ** r.uniform(-2.0, 2.0, n)
-    X = 10.0 ** r.uniform(-2.0, 10.0, n)
+    w = 10.0 ** r.uniform(-0.5, 2.0, n)
+    X = 10.0 ** r.uniform(-2.0, 7.0, n)
     cth = np.cos(r.uniform(0.0, np.pi, n))
     return np.stack([kap, w, X, cth], axis=1)

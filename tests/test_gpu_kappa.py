@@ -131,7 +131,12 @@ def test_mlp_gradient_matches_cpu_backprop(ctx, small_set):
     inp, integ = small_set
     ctx.mlp_init(123)
     logs = np.log10(integ.cpu().numpy())
-    norm = np.concatenate([logs.mean(0), logs.std(0)])
+    # a baseline with nonzero coefficients, so that the residual targets are exercised
+    cb = np.zeros((8, 20))
+    cb[:, 0] = logs.mean(0)
+    cb[:, 3] = 0.5
+    cb[:, 6] = -0.25
+    norm = np.concatenate([np.zeros(8), logs.std(0), cb.ravel()])
     p0, _ = ctx.mlp_get_params()
     ctx.mlp_set_params(p0, norm)
     n = 1000   # ragged: not a multiple of the 32-sample tile
@@ -151,7 +156,10 @@ def test_mlp_mfma_forward_matches_cpu(ctx, small_set):
     inp, integ = small_set
     ctx.mlp_init(7)
     logs = np.log10(integ.cpu().numpy())
-    norm = np.concatenate([logs.mean(0), logs.std(0)])
+    cb = np.zeros((8, 20))
+    cb[:, 2] = 0.3
+    cb[:, 19] = -0.1
+    norm = np.concatenate([logs.mean(0), logs.std(0), cb.ravel()])
     p0, _ = ctx.mlp_get_params()
     ctx.mlp_set_params(p0, norm)
     n = 2048 - 37   # ragged against the 64-lane waves
@@ -165,17 +173,20 @@ def test_mlp_mfma_forward_matches_cpu(ctx, small_set):
 def test_mlp_training_reduces_loss(ctx, small_set):
     inp, integ = small_set
     ctx.mlp_init(11)
-    ctx.mlp_set_params(ctx.mlp_get_params()[0], np.concatenate([np.zeros(8), np.ones(8)]))
-    # loss at the initial weights with the set's normalisation
-    logs = np.log10(integ.cpu().numpy())
-    norm = np.concatenate([logs.mean(0), logs.std(0)])
-    p0, _ = ctx.mlp_get_params()
-    ctx.mlp_set_params(p0, norm)
-    _, loss0 = ctx.mlp_grad(inp, integ)
-    loss = ctx.mlp_train(inp, integ, epochs=40, batch=256, lr_max=3e-3, lr_min=1e-5, seed=3)
+    # one epoch at a vanishing step fits the baseline and gives the initial loss
+    loss0 = ctx.mlp_train(inp, integ, epochs=1, batch=256, lr_max=1e-12, lr_min=0.0, seed=3)
+    _, norm0 = ctx.mlp_get_params()
+    loss = ctx.mlp_train(inp, integ, epochs=40, batch=256, lr_max=3e-3, lr_min=1e-5, seed=3, set_norm=False)
     _log(f"training loss {loss0:.4e} -> {loss:.4e}")
     assert loss < 0.05 * loss0
     p1, norm1 = ctx.mlp_get_params()
-    assert np.allclose(norm1, norm, rtol=1e-12)
+    assert np.array_equal(norm1, norm0)
+    # the fitted baseline is the least-squares cubic of log10 I in the features
+    from oracle import mlp as om
+    M = om.monomials(om.features(inp.cpu().numpy()))
+    y = np.log10(integ.cpu().numpy())
+    c_ls, *_ = np.linalg.lstsq(M, y, rcond=None)
+    assert np.abs(norm1[16:].reshape(8, 20) - c_ls.T).max() < 1e-8 * max(1.0, np.abs(c_ls).max())
+    assert np.allclose(norm1[8:16], (y - M @ c_ls).std(0), rtol=1e-6)
     loss_c = omlp.loss_and_grad(p1.astype(np.float64), norm1, inp.cpu().numpy(), integ.cpu().numpy())[0]
     assert abs(loss_c / loss - 1) < 1e-3

@@ -113,6 +113,7 @@ def test_surrogate_image_flux_within_1e3_of_exact(krt, trained, case):
     prims = desc = None
     if "snapshot" in w:
         desc, seed = w["snapshot"]
+        desc["R_high"] = 1.0     # kappa images: T_e = T_i in the disk (Theta_e 1-100)
         prims = torch.tensor(W.make_snapshot(desc, seed), device="cuda")
     imgs = _images(krt, trained, w["camera"], w["model"], prims, desc)
     Sm, stm = imgs[krt.ELECTRONS_KAPPA_SURROGATE]
@@ -129,10 +130,11 @@ def test_surrogate_image_flux_within_1e3_of_exact(krt, trained, case):
 
 def test_surrogate_gain_over_exact(krt, trained):
     """Rays/s of the surrogate image over the exact-integrator image (256^2
-    image of the small snapshot at 20 degrees, kappa = 5: 1024 tiles, one
-    wave per SIMD)."""
+    image of the small snapshot at 20 degrees, R_high = 1, kappa = 5: 1024
+    tiles, one wave per SIMD)."""
     w = W.workload("snap48")
     desc, seed = w["snapshot"]
+    desc["R_high"] = 1.0
     prims = torch.tensor(W.make_snapshot(desc, seed), device="cuda")
     cam = W.snapshot_camera(256)
     times = {}

@@ -24,7 +24,7 @@ def _set(n, seed):
     inp = np.stack([r.uniform(3, 8, n), 10 ** r.uniform(0, 2, n), 10 ** r.uniform(-2, 6, n),
                     np.cos(r.uniform(0, np.pi, n))], 1)
     integ = 10 ** r.normal(-3, 2, (n, 8))
-    norm = np.concatenate([np.full(8, -3.0), np.linspace(0.5, 3.0, 8)])
+    norm = np.concatenate([np.full(8, -3.0), np.linspace(0.5, 3.0, 8), r.normal(0, 0.5, 160)])
     return inp, integ, norm
 
 
@@ -66,9 +66,9 @@ def test_forward_definition_small_case():
     d["b4"][:] = 0.25
     p = mlp.pack(d)
     inp = np.array([[8.0, 10.0, 100.0, 0.0]])
-    x = (8.0 - 5.5) / 2.5
+    x = (8.0 - 5.5) / 2.5   # exact in FP32
     s = lambda t: t / (1 + np.exp(-t))
     z3 = 4.0 * s(0.5 * s(2.0 * s(x))) + 0.25
-    norm = np.concatenate([np.zeros(8), np.ones(8)])
+    norm = np.concatenate([np.zeros(8), np.ones(8), np.zeros(160)])
     out = mlp.predict_log10(p, norm, inp)[0]
     assert abs(out[3] - z3) < 1e-15 and np.allclose(out[[0, 1, 2, 4, 5, 6, 7]], 0.25, rtol=0, atol=1e-15)
