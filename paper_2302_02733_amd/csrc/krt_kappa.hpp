@@ -135,13 +135,13 @@ constexpr int kKapNodes = 361;
 constexpr double kKapU0 = -20.0;
 constexpr double kKapDu = 0.125;
 
-KRT_HD void kappa_integrals(const double* __restrict__ syntab, double kap, double w, double X, double o[8]) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double norm = 0.0;
+// Contribution of quadrature node i to the normalisation and the eight sums.
+KRT_HD void kappa_node(const double* __restrict__ syntab, double kap, double w, double X, int i, double& norm,
+                       double acc[8]) {
     const double ikw = 1.0 / (kap * w);
     const double kp1 = kap + 1.0;
     const double Xw2 = X * w * w;
-    for (int i = 0; i < kKapNodes; ++i) {
+    {
         const double gm1 = exp(kKapU0 + kKapDu * i);
         const double g = 1.0 + gm1;
         const double p = sqrt(gm1 * (g + 1.0));
@@ -162,8 +162,32 @@ KRT_HD void kappa_integrals(const double* __restrict__ syntab, double kap, doubl
         acc[6] += f * (2.0 * g - ig) * (Xg / (1.0 + Xg));
         acc[7] += f * log1p(gm1 + p) * ig / p;
     }
+}
+
+KRT_HD void kappa_integrals(const double* __restrict__ syntab, double kap, double w, double X, double o[8]) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double norm = 0.0;
+    for (int i = 0; i < kKapNodes; ++i) kappa_node(syntab, kap, w, X, i, norm, acc);
     const double in = 1.0 / norm;
 #pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = acc[k] * in;
+}
+
+// The same integrals for one point, computed by a whole wave: lane l takes
+// the nodes l, l + 64, ..., and the nine sums are reduced across the wave.
+// Every lane passes the same (kap, w, X) and gets the result.  Must be called
+// by all 64 lanes together.
+__device__ __forceinline__ void kappa_integrals_wave(const double* __restrict__ syntab, double kap, double w,
+                                                     double X, double o[8]) {
+    const int lane = threadIdx.x & 63;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double norm = 0.0;
+    for (int i = lane; i < kKapNodes; i += 64) kappa_node(syntab, kap, w, X, i, norm, acc);
+    for (int off = 32; off >= 1; off >>= 1) {
+        norm += __shfl_xor(norm, off);
+        for (int k = 0; k < 8; ++k) acc[k] += __shfl_xor(acc[k], off);
+    }
+    const double in = 1.0 / norm;
     for (int k = 0; k < 8; ++k) o[k] = acc[k] * in;
 }
 

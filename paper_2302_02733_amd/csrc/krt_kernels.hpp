@@ -682,26 +682,43 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
             // surrogate inputs of this lane's point (in-domain points only),
             // the network for the whole wave, then the update
             float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            bool want = false, has = false;
+            bool want = false, has = false, fall = false;
+            double Xp = 0.0;
             Plasma p;
             if (m <= n_end) {
                 double pt[8];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
-                double nu, cth, X, sth;
+                double nu, cth, sth;
                 has = kappa_point(A, pt, p, nu, cth);
-                if (has && kappa_frame(p.ne, p.thetae, p.B, nu, cth, X, sth) &&
-                    mlp_in_domain(A.kappa, p.thetae, X)) {
-                    mlp_features(A.kappa, p.thetae, X, cth, f);
-                    want = true;
+                if (has && kappa_frame(p.ne, p.thetae, p.B, nu, cth, Xp, sth)) {
+                    if (mlp_in_domain(A.kappa, p.thetae, Xp)) {
+                        mlp_features(A.kappa, p.thetae, Xp, cth, f);
+                        want = true;
+                    } else {
+                        fall = true;
+                    }
                 }
             }
             double I[8];
             if (__ballot(want) != 0ull) mlp_wave(A.mlp, f, I);
+            // points outside the surrogate's domain: the exact integrator, one
+            // point at a time with the whole wave on its quadrature nodes
+            unsigned long long fb = __ballot(fall);
+            while (fb != 0ull) {
+                const int src = __ffsll(fb) - 1;
+                fb &= fb - 1ull;
+                const double w_s = __shfl(p.thetae, src), X_s = __shfl(Xp, src);
+                double Iw[8];
+                kappa_integrals_wave(A.syntab, A.kappa, w_s, X_s, Iw);
+                if (lane == src)
+                    for (int k = 0; k < 8; ++k) I[k] = Iw[k];
+            }
             if (m <= n_end) {
                 double pt[8];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 n_mlp += want ? 1u : 0u;
-                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want, n_exact, &p, has);
+                n_exact += fall ? 1u : 0u;
+                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, has);
             }
         } else if (m <= n_end) {
             double pt[8];
