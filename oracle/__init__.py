@@ -9,6 +9,9 @@ Sec. 2.1 of Moscibrodzka & Yfantis (2023): per pixel a backward null geodesic
 with an eps-controlled adaptive step (Sec. 2.2), saved, then covariant fully
 polarized transfer of the coherency matrix along it toward the camera, with
 synchrotron emission, absorption and Faraday coefficients at every point.
+kappa.cpp integrates the coefficients of a kappa electron distribution over
+the Lorentz factor (the nonthermal extension); mlp.py is an FP64 reference of
+the coefficient surrogate network and its backward pass.
 """
 import ctypes
 import os

@@ -255,28 +255,33 @@ KRT_HD void kappa_physical(const double I[8], double ne, double B, double nu, do
 // for small x^2+y^2 (or small x^2, y^2) the same from the Taylor coefficients
 // t_n = f^(n)(-tau) / n!.  exp(-K w) uses the thermal module's coefficients.
 // ---------------------------------------------------------------------------
-// Taylor coefficients of phi1 at z = -tau <= 0: t_n = int_0^1 e^(z s) s^n / n! ds.
+// Taylor coefficients of phi1 at z = -tau <= 0: t_n = int_0^1 e^(z s) s^n / n! ds
+// = e^z sum_k tau^k / (n+k+1)!, linked by t_(n-1) = e^z / n! + tau t_n.  The
+// recurrence is used where it is stable: upward, t_n = (t_(n-1) - e^z/n!) / tau,
+// for n <= tau; downward for n > tau, from n = 80 where t_80 is taken as
+// e^z / (81! (1 - tau/82)) (the error this start leaves is damped by tau/n per
+// step, below 1e-20 by n = 21).  Relative error a few ulp for every tau >= 0.
+constexpr double kInvFact81 = 1.724992688482352e-121;   // 1/81!
+
 KRT_HD void phi1_taylor(double z, double t[22]) {
-    if (z < -1.0) {
-        // forward recurrence z t_n + t_(n-1) = e^z / n! (stable for |z| > 1)
-        const double ez = exp(z);
-        const double iz = 1.0 / z;
-        t[0] = expm1(z) * iz;
-        for (int n = 1; n < 22; ++n) t[n] = (ez * kInvFact[n] - t[n - 1]) * iz;
-    } else {
-        // t_n = sum_j C(n+j, j) z^j / (n+j+1)!  (|z| <= 1: 17 terms give 1e-16)
-        for (int n = 0; n < 22; ++n) {
-            double term = 1.0;                 // C(n+j, j) z^j / (n+j+1)! * (n+1)!
-            double s = 1.0;
-            for (int j = 1; j <= 17; ++j) {
-                term *= z * (double)(n + j) / ((double)j * (double)(n + j + 1));
-                s += term;
-            }
-            // 1 / (n+1)!
-            double f = 1.0;
-            for (int q = 2; q <= n + 1; ++q) f /= (double)q;
-            t[n] = s * f;
+    const double tau = -z;
+    const double ez = exp(z);
+    t[0] = (tau > 0.0) ? expm1(z) / z : 1.0;
+    int m = 0;
+    if (tau >= 1.0) {
+        m = tau >= 21.0 ? 21 : (int)tau;
+        const double it = 1.0 / tau;
+        for (int n = 1; n <= m; ++n) t[n] = (t[n - 1] - ez * kInvFact[n]) * it;
+    }
+    if (m < 21) {
+        double f = kInvFact81 * 81.0;                      // 1/80!
+        double tn = ez * kInvFact81 / (1.0 - tau / 82.0);  // t_80
+        for (int n = 80; n >= 22; --n) {
+            tn = ez * f + tau * tn;                        // t_(n-1)
+            f *= (double)n;
         }
+        t[21] = tn;
+        for (int n = 21; n >= m + 2; --n) t[n - 1] = ez * kInvFact[n] + tau * t[n];
     }
 }
 

@@ -56,7 +56,7 @@ def test_kappa_integrals_match_oracle(ctx):
 def _mueller_cases():
     r = np.random.default_rng(31)
     cases = []
-    for regime in range(6):
+    for regime in range(7):
         for _ in range(24):
             AI = 10 ** r.uniform(-3, 1)
             frac = r.uniform(0, 0.95)
@@ -74,10 +74,14 @@ def _mueller_cases():
                 RQ = RV = 0.0
             elif regime == 4:    # rotation along the dichroism axis (small x or y)
                 RQ, RV = 3.0 * AQ + 1e-3, 3.0 * AV
-            else:                # optically thick
+            elif regime == 5:    # optically thick
                 AI = 10 ** r.uniform(1, 2.5)
                 AQ, AV = AI * 0.5, -AI * 0.3
                 RQ, RV = r.normal(0, 10, 2)
+            else:                # optical depth 1-20 with small invariants (series branch
+                AI = 10 ** r.uniform(0.2, 1.3)    # with high-order Taylor terms of phi1)
+                AQ, AV = r.uniform(-0.2, 0.2, 2)
+                RQ, RV = r.uniform(-0.15, 0.15, 2)
             J = r.normal(0, 1, 3) * 10 ** r.uniform(-2, 1)
             J[0] = abs(J[0]) + np.hypot(J[1], J[2])
             S = r.normal(0, 1, 4)
