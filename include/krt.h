@@ -213,8 +213,10 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
  * 64-lane wave traces, 64 / tile_w rows (4, 8, 16, 32 or 64; default 8);
  * blocks_per_cu: blocks of 256 threads per compute unit in the persistent
  * grid (0: as many as fit); path_cap: points per wave slice of the path store
- * (0: KRT_PATH_CAP or 8192), longer paths continue in chunks; order (batches):
- * 1 queues the groups with most instances first, 0 keeps the given order. */
+ * (0: KRT_PATH_CAP or 8192), longer paths continue in chunks; order: 1 (the
+ * default) queues a plain image's tiles nearest the image centre first (the
+ * longest rays, near the shadow's edge, start first) and a batch's groups
+ * with most instances first; 0 keeps row-major tiles and the given groups. */
 typedef struct {
     uint32_t struct_size;
     int32_t tile_w;

@@ -69,6 +69,10 @@ struct krt_ctx {
     double* mlp_norm = nullptr;
     MlpPacked* mlp_packed = nullptr;
     bool mlp_ready = false;
+    // plain-mode tile order (centre first) for the last image shape
+    int* tile_order = nullptr;
+    int tile_order_cap = 0;
+    int tile_order_key[3] = {0, 0, 0};   // tiles_x, tiles_y, tile_w
     int electrons = KRT_ELECTRONS_THERMAL;
     double kappa = 5.0;
     std::string err;
@@ -381,6 +385,54 @@ krt_status check_ready(krt_ctx* ctx, const krt_camera* cam) {
 }
 
 
+// Queue order of the plain tracer's tiles: by distance of the tile centre
+// from the image centre, nearest first.  Rays near the shadow's edge (near
+// the centre) are the longest; starting them first leaves cheap tiles for
+// the end of the launch (on the 1024^2 ADAF image a simulated schedule of
+// 2048 waves ends 21% after the ideal in row-major order and 5.5% centre
+// first).  Rebuilt when the image shape changes; synchronous upload.
+krt_status ensure_tile_order(krt_ctx* ctx, int tiles_x, int tiles_y, int tile_w, const int** out) {
+    *out = nullptr;
+    if (ctx->cfg.order != 1) return KRT_OK;
+    const int n = tiles_x * tiles_y;
+    if (ctx->tile_order && ctx->tile_order_key[0] == tiles_x && ctx->tile_order_key[1] == tiles_y &&
+        ctx->tile_order_key[2] == tile_w) {
+        *out = ctx->tile_order;
+        return KRT_OK;
+    }
+    if (n > ctx->tile_order_cap) {
+        if (ctx->tile_order) {
+            KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            KRT_HIP(ctx, hipFree(ctx->tile_order));
+            ctx->tile_order = nullptr;
+        }
+        if (hipMalloc(&ctx->tile_order, (size_t)n * sizeof(int)) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->tile_order = nullptr;
+            ctx->tile_order_cap = 0;
+            return fail(ctx, KRT_E_NOMEM, "cannot allocate the tile order");
+        }
+        ctx->tile_order_cap = n;
+    }
+    std::vector<int> ord(n);
+    std::vector<double> d2(n);
+    const int th = 64 / tile_w;
+    const double cx = 0.5 * tiles_x * tile_w, cy = 0.5 * tiles_y * th;
+    for (int t = 0; t < n; ++t) {
+        ord[t] = t;
+        const double x = ((t % tiles_x) + 0.5) * tile_w - cx, y = ((t / tiles_x) + 0.5) * th - cy;
+        d2[t] = x * x + y * y;
+    }
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d2[a] < d2[b]; });
+    KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    KRT_HIP(ctx, hipMemcpy(ctx->tile_order, ord.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice));
+    ctx->tile_order_key[0] = tiles_x;
+    ctx->tile_order_key[1] = tiles_y;
+    ctx->tile_order_key[2] = tile_w;
+    *out = ctx->tile_order;
+    return KRT_OK;
+}
+
 // Synchrotron-function table of the nonthermal module, built on first use.
 krt_status ensure_syntab(krt_ctx* ctx) {
     if (ctx->syntab) return KRT_OK;
@@ -643,6 +695,7 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->red_partial) (void)hipFree(ctx->red_partial);
     if (ctx->btab) (void)hipFree(ctx->btab);
     if (ctx->syntab) (void)hipFree(ctx->syntab);
+    if (ctx->tile_order) (void)hipFree(ctx->tile_order);
     if (ctx->mlp_P) (void)hipFree(ctx->mlp_P);
     if (ctx->mlp_m) (void)hipFree(ctx->mlp_m);
     if (ctx->mlp_v) (void)hipFree(ctx->mlp_v);
@@ -736,6 +789,7 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     if ((st = ensure_chunks(ctx)) != KRT_OK) return st;
     if ((st = ensure_long(ctx, cam->max_steps, npix)) != KRT_OK) return st;
     TraceArgs A = base_args(ctx, cam);
+    if ((st = ensure_tile_order(ctx, A.tiles_x, A.nbatch / A.tiles_x, A.tile_w, &A.tile_order)) != KRT_OK) return st;
     A.kappa = ctx->kappa;
     A.syntab = ctx->syntab;
     A.mlp = ctx->mlp_packed;

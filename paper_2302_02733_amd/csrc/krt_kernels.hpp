@@ -51,6 +51,7 @@ struct TraceArgs {
     int tiles_x, nbatch;
     int tile_w;         // pixels per tile row; a tile is tile_w x (64 / tile_w)
     unsigned* queue;    // [0]: next tile (or batch item)
+    const int* tile_order;  // plain mode: queue position -> tile (null: row-major)
     // paged extension of the wave store: chunks of `cap` points x 64 lanes,
     // taken by a wave whose rays outgrow its slice, returned after the tile
     double* chunk_pool;
@@ -858,8 +859,9 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : 2) void trace_waves(TraceA
         // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
         // as a scalar, so the loop exit below is wave-uniform.
         const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
-        const int tile = __builtin_amdgcn_readfirstlane((int)ticket);
-        if (tile >= A.nbatch) break;
+        const int pos = __builtin_amdgcn_readfirstlane((int)ticket);
+        if (pos >= A.nbatch) break;
+        const int tile = A.tile_order ? A.tile_order[pos] : pos;
         int i, j;
         tile_pixel(A.tiles_x, A.tile_w, tile, lane, i, j);
         const bool valid = i < A.cam.nx && j < A.cam.ny;
