@@ -39,6 +39,10 @@ TRAFFIC_WORKLOAD = "adaf1024"
 HBM_PEAK_GBS = 8000.0
 
 
+def fprs_for(args):
+    return FLOPS_PER_RAY_STEP_F32 if args.precision == "fp32" else FLOPS_PER_RAY_STEP
+
+
 def run_probe(kind, precision="fp64"):
     import torch
     from paper_2302_02733_amd import krt
@@ -261,6 +265,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="fp32: FP32 transfer operators with FP64 geodesics and FP64 transfer state "
                          "(and the FP32 copy of the snapshot)")
+    ap.add_argument("--no-4096", action="store_true",
+                    help="adaf1024: skip the companion 4096x4096 measurement")
     ap.add_argument("--kappa-compare", type=int, default=0,
                     help="kappa workloads: also trace an N x N image with the exact integrator everywhere")
     ap.add_argument("--flop-probe", action="store_true")
@@ -329,6 +335,27 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stats = out["stats"]
+        big = None
+        if args.workload == "adaf1024" and not args.no_4096:
+            # the same model at 4096 x 4096 (the metric's second size), after
+            # the timed region: 1 warm-up and 2 timed traces
+            c4 = W.workload("adaf4096")["camera"]
+            s4 = torch.empty((4, c4["ny"], c4["nx"]), dtype=torch.float64, device=dev)
+            ctx.trace(c4, stokes=s4, stats=False)
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            k4 = []
+            for _ in range(2):
+                o4 = ctx.trace(c4, stokes=s4)
+                k4.append(o4["stats"]["kernel_ms"][0])
+            torch.cuda.synchronize()
+            d4 = (time.perf_counter() - t4) / 2
+            big = {"pixels": c4["nx"] * c4["ny"], "rays_per_s": c4["nx"] * c4["ny"] / d4, "ms_per_image": 1e3 * d4,
+                   "kernel_ms": sum(k4) / 2,
+                   "frac_of_fp64_peak": (fprs_for(args) * o4["stats"]["total_steps"] / (sum(k4) / 2 * 1e-3) / 1e12
+                                         / FP64_PEAK_TFLOPS) if fprs_for(args) else None}
+            print(f"4096x4096: {1e3 * d4:.1f} ms per image", file=sys.stderr, flush=True)
+            del s4
 
     ms_per_step = 1e3 * dt / args.steps
     kernel_ms = sum(kms) / len(kms)
@@ -369,6 +396,8 @@ def main():
         "flux_jy": flux,
         "roofline": roof,
     }
+    if big is not None:
+        line["adaf4096"] = big
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, snap_host)
     print(json.dumps(line))
