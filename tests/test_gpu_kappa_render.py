@@ -154,3 +154,43 @@ def test_surrogate_gain_over_exact(krt, trained):
     _log(f"surrogate {times[krt.ELECTRONS_KAPPA_SURROGATE] * 1e3:.1f} ms, exact "
          f"{times[krt.ELECTRONS_KAPPA_EXACT] * 1e3:.1f} ms per 256^2 image: gain {gain:.1f}x")
     assert gain > 1.5
+
+
+def test_surrogate_full_size_sampled_against_oracle(krt, trained):
+    """The kappa workload at its full size (288x128x128 snapshot, 4096x4096,
+    R_high = 1, kappa = 5, surrogate mode as the bench runs it), checked on
+    sampled pixels against the oracle's exact kappa coefficients: identical
+    status and step counts, per-pixel error within the surrogate's accuracy."""
+    desc = W.snapshot_desc(R_high=1.0)
+    P = W.make_snapshot(desc, 7)
+    cam = W.snapshot_camera(4096)
+    prims = torch.tensor(P, device="cuda")
+    with krt.Context(0) as ctx:
+        trained.load(ctx)
+        ctx.set_units(W.UNITS)
+        ctx.set_model_snapshot(desc, prims)
+        ctx.set_electrons(krt.ELECTRONS_KAPPA_SURROGATE, KAPPA)
+        ns = torch.empty((4096, 4096), dtype=torch.int32, device="cuda")
+        _log("kappa surrogate trace 4096x4096")
+        out = ctx.trace(cam, nsteps=ns)
+        torch.cuda.synchronize()
+        _log(f"trace done: {out['stats']}")
+        pix = W.pixel_sample(4096, 4096, 48, 4099)
+        # pixels near the image centre carry the emission; add a central block
+        c = [2048 * 4096 + 2048 + k for k in (-300, -100, 0, 100, 300)]
+        pix = np.unique(np.concatenate([pix, c]))
+        idx = torch.tensor(pix, device="cuda")
+        S = out["stokes"].reshape(4, -1)[:, idx].cpu().numpy()
+        st = out["status"].reshape(-1)[idx].cpu().numpy()
+        nsv = ns.reshape(-1)[idx].cpu().numpy()
+        imax = float(out["stokes"][0].max())
+    h = oracle.SnapshotHandle(desc, P)
+    _log(f"oracle kappa render of {len(pix)} pixels")
+    So, sto, nso = oracle.render(cam, W.UNITS, {"kind": 3, "electrons": 1, "kappa": KAPPA}, snap=h, pixels=pix)
+    assert np.array_equal(st, sto) and np.array_equal(nsv, nso)
+    err = np.abs(S - So).max(0) / imax
+    rel = np.abs(S[0] - So[0]) / np.maximum(So[0], 1e-300)
+    _log(f"max |dS|/Imax {err.max():.2e}; I rel err on emitting pixels "
+         f"{np.max(rel[So[0] > 1e-3 * imax]) if np.any(So[0] > 1e-3 * imax) else 0:.2e}")
+    assert err.max() <= 3e-3
+    assert np.all(rel[So[0] > 1e-3 * imax] <= 1e-2)
