@@ -678,6 +678,11 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
     for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
     for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
     unsigned n_mlp = 0, n_exact = 0;
+    // Modes with registers to spare load each stored point one point ahead;
+    // in the FP64 mode (256 registers) the extra 16 would spill.
+    constexpr bool kPrefetch = kMode == kModeF32 || kMode == kModeKapExact;
+    double nxt[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr(A, slot, wchunks, nmax, lane), nxt);
     for (int m = nmax; m >= 0; --m) {
         if constexpr (kMode == kModeKapMlp) {
             // surrogate inputs of this lane's point (in-domain points only),
@@ -721,9 +726,18 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
                 n_exact += fall ? 1u : 0u;
                 transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, has);
             }
-        } else if (m <= n_end) {
+        } else {
             double pt[8];
-            load_point(point_addr(A, slot, wchunks, m, lane), pt);
+            if constexpr (kPrefetch) {
+                // the next point (m - 1) is loaded while this one is processed
+#pragma unroll
+                for (int k = 0; k < 8; ++k) pt[k] = nxt[k];
+                if (m >= 1 && m - 1 <= n_end) load_point(point_addr(A, slot, wchunks, m - 1, lane), nxt);
+                if (m > n_end) continue;
+            } else {
+                if (m > n_end) continue;
+                load_point(point_addr(A, slot, wchunks, m, lane), pt);
+            }
             TraceArgs L = A;
             launder_transfer(L);
             if constexpr (kMode == kModeF32)
@@ -850,7 +864,10 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : 2) void trace_waves(TraceA
         A.mlp = reinterpret_cast<const MlpPacked*>(s_mlp);
     }
     const int lane = threadIdx.x & 63;
-    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the wave index is uniform: read it from the first lane so that the
+    // slice address lives in scalar registers
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) +
+                        (size_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
     __shared__ int s_chunks[4][kMaxChunks];
     int* wchunks = s_chunks[threadIdx.x >> 6];
@@ -956,7 +973,10 @@ __global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
     __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
     stage_table<kMode>(A, s_btab, s_btab_f);
     const int lane = threadIdx.x & 63;
-    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // the wave index is uniform: read it from the first lane so that the
+    // slice address lives in scalar registers
+    const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) +
+                        (size_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
     __shared__ int s_chunks[4][kMaxChunks];
     int* wchunks = s_chunks[threadIdx.x >> 6];
