@@ -34,7 +34,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 # HBM bytes per ray-step of trace_waves on the 1024^2 ADAF image: rocprofv3
 # FETCH_SIZE and WRITE_SIZE of one launch, each scaled by what the counter
 # reads for a copy of known size, divided by the launch's ray-steps.
-TRAFFIC_BYTES_PER_RAY_STEP = 128.4
+TRAFFIC_BYTES_PER_RAY_STEP = 128.2
 TRAFFIC_WORKLOAD = "adaf1024"
 HBM_PEAK_GBS = 8000.0
 
