@@ -356,6 +356,25 @@ def main():
                                          / FP64_PEAK_TFLOPS) if fprs_for(args) else None}
             print(f"4096x4096: {1e3 * d4:.1f} ms per image", file=sys.stderr, flush=True)
             del s4
+        vs64 = None
+        if f32:
+            # the same image in the FP64 path (FP64 primitives for a snapshot),
+            # after the timed region: error of the mixed-precision image and
+            # the kernel-time ratio
+            if prims is not None:
+                ctx.set_model_snapshot(w["snapshot"][0],
+                                       torch.tensor(W.make_snapshot(*w["snapshot"]), device=dev))
+            ctx.set_precision(krt.PRECISION_FP64)
+            s64 = torch.empty_like(stokes)
+            ctx.trace(cam, stokes=s64, stats=False)
+            o64 = ctx.trace(cam, stokes=s64)
+            f64, _ = ctx.reduce(s64, cam)
+            im = float(s64[0].max())
+            d = (stokes - s64).abs().reshape(4, -1) / im
+            p99 = torch.quantile(d[:, :: max(1, d.shape[1] // (1 << 20))], 0.99, dim=1).tolist()
+            vs64 = {"flux_rel_err": [abs(flux[k] - f64[k]) / abs(f64[0]) for k in range(4)],
+                    "p99_dS_over_Imax": p99, "fp64_kernel_ms": o64["stats"]["kernel_ms"][0]}
+            print(f"FP64 image for comparison: {vs64}", file=sys.stderr, flush=True)
 
     ms_per_step = 1e3 * dt / args.steps
     kernel_ms = sum(kms) / len(kms)
@@ -398,6 +417,9 @@ def main():
     }
     if big is not None:
         line["adaf4096"] = big
+    if vs64 is not None:
+        vs64["speedup"] = vs64["fp64_kernel_ms"] / kernel_ms
+        line["vs_fp64"] = vs64
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, snap_host)
     print(json.dumps(line))
