@@ -273,7 +273,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the path has no multi-GPU mode); "
+        print("bench.py: the tracer runs on one GPU (it has no multi-GPU mode); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     if args.flop_probe or args.copy_probe:
