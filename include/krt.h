@@ -216,7 +216,12 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
  * (0: KRT_PATH_CAP or 8192), longer paths continue in chunks; order: 1 (the
  * default) queues a plain image's tiles nearest the image centre first (the
  * longest rays, near the shadow's edge, start first) and a batch's groups
- * with most instances first; 0 keeps row-major tiles and the given groups. */
+ * with most instances first; 0 keeps row-major tiles and the given groups;
+ * 2 splits a plain image into 8 sectors of 45 degrees around its centre,
+ * one per XCD, each queued centre-first and taken first by the waves of
+ * that XCD (blocks dealt to the XCDs in turn), which keep a sector's
+ * snapshot cells in one L2 (batches: as 1).  The order never changes an
+ * image; order is validated to 0, 1 or 2 (KRT_E_INVAL otherwise). */
 typedef struct {
     uint32_t struct_size;
     int32_t tile_w;

@@ -55,7 +55,8 @@ struct krt_ctx {
     size_t batch_dev_bytes = 0;
     void* batch_host = nullptr;
     size_t batch_host_bytes = 0;
-    // counters: [0] tile queue, [1] overflow count (unsigned); then 10 x u64
+    // counters: [0] tile queue, [1] overflow count (unsigned); then 10 x u64;
+    // then the 8 sector queues
     unsigned* work = nullptr;
     double* red_partial = nullptr;
     double* host_buf = nullptr;  // pinned, 16 doubles
@@ -72,7 +73,7 @@ struct krt_ctx {
     // plain-mode tile order (centre first) for the last image shape
     int* tile_order = nullptr;
     int tile_order_cap = 0;
-    int tile_order_key[3] = {0, 0, 0};   // tiles_x, tiles_y, tile_w
+    int tile_order_key[4] = {0, 0, 0, 0};   // tiles_x, tiles_y, tile_w, sectors
     int electrons = KRT_ELECTRONS_THERMAL;
     double kappa = 5.0;
     std::string err;
@@ -80,7 +81,8 @@ struct krt_ctx {
 
 namespace {
 
-constexpr int kWorkWords = 2 + 2 * 10;
+constexpr int kSectors = 8;   // XCDs of the device: one image sector each
+constexpr int kWorkWords = 2 + 2 * 10 + kSectors;
 constexpr int kRedBlocks = 1024;
 
 krt_status fail(krt_ctx* ctx, krt_status code, const std::string& msg) {
@@ -203,6 +205,8 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     A.tiles_x = (cam->nx + tw - 1) / tw;
     A.nbatch = A.tiles_x * ((cam->ny + 64 / tw - 1) / (64 / tw));
     A.queue = ctx->work;
+    A.squeue = ctx->work + 2 + 2 * 10;
+    A.nsec = 1;
     A.overflow_count = ctx->work + 1;
     A.counters = reinterpret_cast<unsigned long long*>(ctx->work + 2);
     return A;
@@ -391,30 +395,38 @@ krt_status check_ready(krt_ctx* ctx, const krt_camera* cam) {
 // the end of the launch (on the 1024^2 ADAF image a simulated schedule of
 // 2048 waves ends 21% after the ideal in row-major order and 5.5% centre
 // first).  Rebuilt when the image shape changes; synchronous upload.
-krt_status ensure_tile_order(krt_ctx* ctx, int tiles_x, int tiles_y, int tile_w, const int** out) {
+krt_status ensure_tile_order(krt_ctx* ctx, int tiles_x, int tiles_y, int tile_w, const int** out,
+                             int* nsec) {
     *out = nullptr;
-    if (ctx->cfg.order != 1) return KRT_OK;
+    *nsec = 1;
+    if (ctx->cfg.order != 1 && ctx->cfg.order != 2) return KRT_OK;
+    const int sectors = ctx->cfg.order == 2 ? kSectors : 1;
     const int n = tiles_x * tiles_y;
+    const int head = sectors > 1 ? sectors + 1 : 0;
     if (ctx->tile_order && ctx->tile_order_key[0] == tiles_x && ctx->tile_order_key[1] == tiles_y &&
-        ctx->tile_order_key[2] == tile_w) {
+        ctx->tile_order_key[2] == tile_w && ctx->tile_order_key[3] == sectors) {
         *out = ctx->tile_order;
+        *nsec = sectors;
         return KRT_OK;
     }
-    if (n > ctx->tile_order_cap) {
+    if (n + head > ctx->tile_order_cap) {
         if (ctx->tile_order) {
             KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
             KRT_HIP(ctx, hipFree(ctx->tile_order));
             ctx->tile_order = nullptr;
         }
-        if (hipMalloc(&ctx->tile_order, (size_t)n * sizeof(int)) != hipSuccess) {
+        if (hipMalloc(&ctx->tile_order, (size_t)(n + kSectors + 1) * sizeof(int)) != hipSuccess) {
             (void)hipGetLastError();
             ctx->tile_order = nullptr;
             ctx->tile_order_cap = 0;
             return fail(ctx, KRT_E_NOMEM, "cannot allocate the tile order");
         }
-        ctx->tile_order_cap = n;
+        ctx->tile_order_cap = n + kSectors + 1;
     }
-    std::vector<int> ord(n);
+    // centre-first: tiles by distance of their centre from the image centre;
+    // with sectors, first by the 45-degree sector of the image around its
+    // centre that holds the tile centre
+    std::vector<int> ord(n), sec(n, 0);
     std::vector<double> d2(n);
     const int th = 64 / tile_w;
     const double cx = 0.5 * tiles_x * tile_w, cy = 0.5 * tiles_y * th;
@@ -422,14 +434,30 @@ krt_status ensure_tile_order(krt_ctx* ctx, int tiles_x, int tiles_y, int tile_w,
         ord[t] = t;
         const double x = ((t % tiles_x) + 0.5) * tile_w - cx, y = ((t / tiles_x) + 0.5) * th - cy;
         d2[t] = x * x + y * y;
+        if (sectors > 1) {
+            const double ang = std::atan2(y, x) + kPi;   // [0, 2 pi]
+            int s = (int)(ang * (sectors / (2.0 * kPi)));
+            sec[t] = s < 0 ? 0 : (s >= sectors ? sectors - 1 : s);
+        }
     }
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d2[a] < d2[b]; });
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int a, int b) { return sec[a] != sec[b] ? sec[a] < sec[b] : d2[a] < d2[b]; });
+    std::vector<int> buf(head + n);
+    if (sectors > 1) {
+        std::vector<int> cnt(sectors, 0);
+        for (int t = 0; t < n; ++t) ++cnt[sec[t]];
+        buf[0] = 0;
+        for (int s = 0; s < sectors; ++s) buf[s + 1] = buf[s] + cnt[s];
+    }
+    for (int k = 0; k < n; ++k) buf[head + k] = ord[k];
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    KRT_HIP(ctx, hipMemcpy(ctx->tile_order, ord.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice));
+    KRT_HIP(ctx, hipMemcpy(ctx->tile_order, buf.data(), buf.size() * sizeof(int), hipMemcpyHostToDevice));
     ctx->tile_order_key[0] = tiles_x;
     ctx->tile_order_key[1] = tiles_y;
     ctx->tile_order_key[2] = tile_w;
+    ctx->tile_order_key[3] = sectors;
     *out = ctx->tile_order;
+    *nsec = sectors;
     return KRT_OK;
 }
 
@@ -789,7 +817,8 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     if ((st = ensure_chunks(ctx)) != KRT_OK) return st;
     if ((st = ensure_long(ctx, cam->max_steps, npix)) != KRT_OK) return st;
     TraceArgs A = base_args(ctx, cam);
-    if ((st = ensure_tile_order(ctx, A.tiles_x, A.nbatch / A.tiles_x, A.tile_w, &A.tile_order)) != KRT_OK) return st;
+    if ((st = ensure_tile_order(ctx, A.tiles_x, A.nbatch / A.tiles_x, A.tile_w, &A.tile_order, &A.nsec)) != KRT_OK)
+        return st;
     A.kappa = ctx->kappa;
     A.syntab = ctx->syntab;
     A.mlp = ctx->mlp_packed;
@@ -846,7 +875,7 @@ krt_status krt_set_launch_config(krt_ctx* ctx, const krt_launch_config* cfg) {
     if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 16) return fail(ctx, KRT_E_INVAL, "blocks_per_cu must be 0..16");
     if (cfg->path_cap != 0 && (cfg->path_cap < 64 || cfg->path_cap > 65536))
         return fail(ctx, KRT_E_INVAL, "path_cap must be 0 or 64..65536");
-    if (cfg->order != 0 && cfg->order != 1) return fail(ctx, KRT_E_INVAL, "order must be 0 or 1");
+    if (cfg->order < 0 || cfg->order > 2) return fail(ctx, KRT_E_INVAL, "order must be 0, 1 or 2");
     ctx->cfg = *cfg;
     return KRT_OK;
 }
@@ -889,7 +918,7 @@ krt_status krt_trace_batch(krt_ctx* ctx, const krt_camera* groups, int32_t ngrou
     // queue order of the groups: most instances first (their tiles cost most)
     std::vector<int> gorder(ngroups);
     for (int g = 0; g < ngroups; ++g) gorder[g] = g;
-    if (ctx->cfg.order == 1)
+    if (ctx->cfg.order >= 1)
         std::stable_sort(gorder.begin(), gorder.end(), [&](int x, int y) { return count[x] > count[y]; });
     std::vector<int> gpos(ngroups);
     for (int k = 0; k < ngroups; ++k) gpos[gorder[k]] = k;

@@ -52,6 +52,10 @@ struct TraceArgs {
     int tile_w;         // pixels per tile row; a tile is tile_w x (64 / tile_w)
     unsigned* queue;    // [0]: next tile (or batch item)
     const int* tile_order;  // plain mode: queue position -> tile (null: row-major)
+    // sectors (plain mode, nsec > 1): tile_order holds nsec + 1 sector bounds,
+    // then the tiles sector by sector; squeue[s] is sector s's next position
+    unsigned* squeue;
+    int nsec;
     // paged extension of the wave store: chunks of `cap` points x 64 lanes,
     // taken by a wave whose rays outgrow its slice, returned after the tile
     double* chunk_pool;
@@ -871,14 +875,33 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : 2) void trace_waves(TraceA
     double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
     __shared__ int s_chunks[4][kMaxChunks];
     int* wchunks = s_chunks[threadIdx.x >> 6];
+    // With sectors, blocks are dealt to the XCDs in turn (block b on XCD
+    // b mod 8), so a wave starts on the sector of its XCD, whose tiles lie
+    // together on the image (and their snapshot cells in that XCD's L2), and
+    // moves on to the next sectors when its own is drained.
+    const int nsec = A.nsec;
+    int sec = nsec > 1 ? (int)(blockIdx.x % (unsigned)nsec) : 0;
+    int drained = 0;
     for (;;) {
         // One queue ticket per wave, taken without a lane-divergent branch:
         // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
         // as a scalar, so the loop exit below is wave-uniform.
-        const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
+        unsigned* q = nsec > 1 ? A.squeue + sec : A.queue;
+        const unsigned ticket = atomicAdd(q, lane == 0 ? 1u : 0u);
         const int pos = __builtin_amdgcn_readfirstlane((int)ticket);
-        if (pos >= A.nbatch) break;
-        const int tile = A.tile_order ? A.tile_order[pos] : pos;
+        int tile;
+        if (nsec > 1) {
+            const int b0 = A.tile_order[sec], b1 = A.tile_order[sec + 1];
+            if (pos >= b1 - b0) {
+                if (++drained == nsec) break;
+                sec = sec + 1 == nsec ? 0 : sec + 1;
+                continue;
+            }
+            tile = A.tile_order[nsec + 1 + b0 + pos];
+        } else {
+            if (pos >= A.nbatch) break;
+            tile = A.tile_order ? A.tile_order[pos] : pos;
+        }
         int i, j;
         tile_pixel(A.tiles_x, A.tile_w, tile, lane, i, j);
         const bool valid = i < A.cam.nx && j < A.cam.ny;

@@ -176,6 +176,36 @@ def test_tile_shapes_match_oracle(krt, tile_w):
         assert np.array_equal(ns.cpu().numpy(), nso)
 
 
+def test_tile_orders_give_identical_images(krt):
+    """Row-major, centre-first and per-XCD sector queues (order 0, 1, 2) only
+    change which wave traces which tile: identical images, bit for bit.  The
+    ragged 37 x 23 image has 15 tiles, so most of the 8 sectors are empty."""
+    cam = W.adaf_camera(37, fov=30.0)
+    cam.update(ny=23, fov_y=20.0, seed=99)
+    big = W.adaf_camera(256, fov=30.0)
+    So, sto, nso = oracle.render(cam, W.UNITS, W.ADAF)
+    with krt.Context(0) as ctx:
+        ctx.set_units(W.UNITS)
+        ctx.set_model(W.ADAF)
+        with pytest.raises(krt.KrtError):
+            ctx.set_launch_config(order=3)
+        out = {}
+        for order in (0, 1, 2):
+            ctx.set_launch_config(order=order)
+            assert ctx.get_launch_config()["order"] == order
+            ns = torch.empty((23, 37), dtype=torch.int32, device="cuda")
+            r = ctx.trace(cam, nsteps=ns)
+            rb = ctx.trace(big)
+            torch.cuda.synchronize()
+            out[order] = (r["stokes"].cpu().numpy(), r["status"].cpu().numpy(), ns.cpu().numpy(),
+                          rb["stokes"].cpu().numpy())
+    _parity(out[2][0], So)
+    assert np.array_equal(out[2][1], sto) and np.array_equal(out[2][2], nso)
+    for order in (0, 1):
+        for k in range(4):
+            assert np.array_equal(out[order][k], out[2][k])
+
+
 def test_autotune_picks_a_candidate_and_caches_it(krt, snap, tmp_path):
     desc, P = snap
     t = torch.tensor(P, device="cuda")
