@@ -255,11 +255,16 @@ void fill_f32(krt_ctx* ctx, double nu, TraceArgs& A) {
 // wavefront of the persistent grid of the kernel about to run (as many blocks
 // as fit on the device, within the KRT_POOL_GB budget).  The store only grows.
 template <int kMode>
-krt_status ensure_pool(krt_ctx* ctx) {
+krt_status ensure_pool(krt_ctx* ctx, bool batch = false) {
     const int cap = ctx->cfg.path_cap > 0 ? ctx->cfg.path_cap : env_int("KRT_PATH_CAP", 8192);
     const double budget_gb = (double)env_int("KRT_POOL_GB", 96);
     int per_cu = 0;
-    KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<kMode>, 256, 0));
+    if (batch) {
+        if constexpr (kMode == kModeF64 || kMode == kModeF32)
+            KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_batch<kMode>, 256, 0));
+    } else {
+        KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<kMode>, 256, 0));
+    }
     if (per_cu < 1) per_cu = 1;
     if (ctx->cfg.blocks_per_cu > 0 && ctx->cfg.blocks_per_cu < per_cu) per_cu = ctx->cfg.blocks_per_cu;
     int blocks = per_cu * ctx->cu_count;
@@ -924,7 +929,7 @@ krt_status krt_trace_batch(krt_ctx* ctx, const krt_camera* groups, int32_t ngrou
     for (int k = 0; k < ngroups; ++k) gpos[gorder[k]] = k;
     KRT_HIP(ctx, hipSetDevice(ctx->device));
     const bool f32 = ctx->precision == KRT_PRECISION_FP32_TRANSFER;
-    if ((st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx)) != KRT_OK) return st;
+    if ((st = f32 ? ensure_pool<kModeF32>(ctx, true) : ensure_pool<kModeF64>(ctx, true)) != KRT_OK) return st;
     if ((st = ensure_chunks(ctx)) != KRT_OK) return st;
     int max_steps = 1;
     for (int g = 0; g < ngroups; ++g) max_steps = std::max(max_steps, (int)groups[g].max_steps);

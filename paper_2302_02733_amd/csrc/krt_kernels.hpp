@@ -344,6 +344,9 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
         }
     }
 
+    // (here only for n > 0: writing it also at n = 0, as the other modes do,
+    // frees registers in the radiative update but gave no speed at two waves
+    // per SIMD)
     if (n > 0) {
         Coh F;
         transport_rhs(Ac, N, F);
@@ -449,7 +452,9 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
             }
         }
     }
-    if (n > 0) {
+    {   // also at n = 0 (D_0 = 0): the state is always written, so that the
+        // incoming state is dead during the radiative update (55 fewer live
+        // registers there than with the write skipped at n = 0)
         Coh F;
         transport_rhs(Ac, N, F);
         const double hh = 0.5 * Dn;
@@ -548,7 +553,8 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bo
         }
     }
 
-    if (n > 0) {
+    {   // also at n = 0 (D_0 = 0): the state is always written, so that the
+        // incoming state is dead during the radiative update
         CohF Nf;
         to_scaled_f(N, Nf);
         transport_rhs_f(Ac, Nf, st.F);
@@ -682,9 +688,10 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
     for (int k = 0; k < 10; ++k) N.R[k] = 0.0;
     for (int k = 0; k < 6; ++k) N.I[k] = 0.0;
     unsigned n_mlp = 0, n_exact = 0;
-    // Modes with registers to spare load each stored point one point ahead;
-    // in the FP64 mode (256 registers) the extra 16 would spill.
-    constexpr bool kPrefetch = kMode == kModeF32 || kMode == kModeKapExact;
+    // The exact-kappa mode (one wave per SIMD, registers to spare) loads each
+    // stored point one point ahead; in the thermal modes, with two or three
+    // waves per SIMD covering the load, it gains nothing.
+    constexpr bool kPrefetch = kMode == kModeKapExact;
     double nxt[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr(A, slot, wchunks, nmax, lane), nxt);
     for (int m = nmax; m >= 0; --m) {
@@ -851,10 +858,12 @@ __device__ __forceinline__ void stage_table(TraceArgs& A, double* s_btab, float*
 // operators, or (kModeGeo) the geodesic phase only, writing the end state (no
 // store, no transfer).  Two waves per SIMD (at most 256 registers per lane):
 // with one, the FP64 dependency chains of a single wave leave the vector ALU
-// idle.
+// idle.  The FP32-operator mode (162 registers) runs three; the FP64 mode
+// (256) would spill heavily at the 168 that three allow.  The kappa modes
+// run one.
 // ---------------------------------------------------------------------------
 template <int kMode>
-__global__ __launch_bounds__(256, kKappa<kMode> ? 1 : 2) void trace_waves(TraceArgs A) {
+__global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2)) void trace_waves(TraceArgs A) {
     constexpr bool kGeoOnly = kMode == kModeGeo;
     constexpr int kTab = kBesPanels * 2 * kBesCoef;
     __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
