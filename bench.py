@@ -28,13 +28,13 @@ if ROOT not in sys.path:
 FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "3113.0"))
 # Same for the FP32-operator transfer (FP64 plus FP32 VALU operations; both run
 # at the same per-lane rate without packed FP32).
-FLOPS_PER_RAY_STEP_F32 = 2854.3
+FLOPS_PER_RAY_STEP_F32 = 2854.5
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 
 # HBM bytes per ray-step of trace_waves on the 1024^2 ADAF image: rocprofv3
 # FETCH_SIZE and WRITE_SIZE of one launch, each scaled by what the counter
 # reads for a copy of known size, divided by the launch's ray-steps.
-TRAFFIC_BYTES_PER_RAY_STEP = 128.2
+TRAFFIC_BYTES_PER_RAY_STEP = 128.3
 TRAFFIC_WORKLOAD = "adaf1024"
 HBM_PEAK_GBS = 8000.0
 
