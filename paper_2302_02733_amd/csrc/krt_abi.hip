@@ -197,6 +197,8 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
     A.adaf.T0 = ctx->adaf.T0_K;
     A.adaf.beta = ctx->adaf.beta;
     A.adaf.h = ctx->adaf.h_over_r;
+    A.adaf.ibeta = 1.0 / ctx->adaf.beta;                                  // beta > 0 (checked)
+    A.adaf.i2h2 = 1.0 / (2.0 * ctx->adaf.h_over_r * ctx->adaf.h_over_r);   // h > 0 (checked)
     A.adaf.risco = isco(cam->a);
     A.btab = ctx->btab;
     fill_f32(ctx, cam->freq_hz, A);

@@ -348,6 +348,7 @@ struct Plasma {
 
 struct AdafDesc {
     double n0, T0, beta, h, risco;
+    double ibeta, i2h2;   // 1 / beta and 1 / (2 h^2), formed on the host
 };
 
 // Analytic ADAF-like flow.  Returns false where no timelike flow exists.
@@ -355,9 +356,10 @@ KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const 
                         Plasma& p) {
     const double c = g.c;
     const double sr = sqrt(r);
-    p.ne = ad.n0 * rcp_fast(r * sr) * exp(-c * c / (2.0 * ad.h * ad.h));
-    p.thetae = kKB * (ad.T0 / r) / (kME * kC * kC);
-    p.B = sqrt(8.0 * kPi * p.ne * kMP * kC * kC / (6.0 * r * ad.beta));
+    const double ir = rcp_fast(r);
+    p.ne = ad.n0 * rcp_fast(r * sr) * exp(-c * c * ad.i2h2);
+    p.thetae = (kKB / (kME * kC * kC)) * ad.T0 * ir;
+    p.B = sqrt((8.0 * kPi * kMP * kC * kC / 6.0) * p.ne * ir * ad.ibeta);
     double Om = 0.0, norm = 1.0;
     const bool kepler = (m != 0.0) && (r >= ad.risco);
     if (kepler) {
@@ -614,19 +616,22 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     double jQ = pre * IQ;
     // j_V = 2 ne e^2 nu cot(theta_B) IV / (3 sqrt3 c Theta^3) = pre (4/3) cot(theta_B) IV / Theta
     double jV = pre * (4.0 / 3.0) * (cth * rcp_fast(sth)) * iTh * IV;
-    const double jP = hypot(jQ, jV);
-    if (jP > jI) {
-        const double sc = jI / jP;
+    // clamp |j_P| <= j_I, compared in squares where they stay normal numbers
+    // (j_I in 1e-140..1e140, |j_Q|, |j_V| below 1e10 j_I); hypot elsewhere
+    const bool sq = jI > 1e-140 && jI < 1e140;
+    if (sq ? (jQ * jQ + jV * jV > jI * jI) : (hypot(jQ, jV) > jI)) {
+        const double sc = jI / hypot(jQ, jV);
         jQ *= sc;
         jV *= sc;
     }
     out[0] = jI;
     out[1] = jQ;
     out[2] = jV;
-    const double seq = kSrcFac / expm1(kHnuOverTheta * nu * iTh);
+    const double em1 = expm1(kHnuOverTheta * nu * iTh);
+    const double seq = kSrcFac / em1;
     const double Bnu = seq * nu * nu * nu;
     if (jI > 0.0 && Bnu > 0.0) {
-        const double iB = 1.0 / Bnu;
+        const double iB = em1 * (1.0 / kSrcFac) * inu2 * inu;   // 1 / B_nu
         out[3] = jI * iB;
         out[4] = jQ * iB;
         out[5] = jV * iB;
@@ -676,12 +681,14 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
     const double q = 0.5 * (a2 - r2);
     const double rad = sqrt(q * q + ar * ar);
     double X, Y;  // x^2 and y^2
+    // (the smaller invariant is at most the larger one: below 1e-290 it is
+    // taken as 0, which keeps the hardware reciprocal off subnormal inputs)
     if (q >= 0.0) {
         X = rad + q;
-        Y = (X > 0.0) ? ar * ar / X : 0.0;
+        Y = (X > 1e-290) ? ar * ar * rcp_fast(X) : 0.0;
     } else {
         Y = rad - q;
-        X = (Y > 0.0) ? ar * ar / Y : 0.0;
+        X = (Y > 1e-290) ? ar * ar * rcp_fast(Y) : 0.0;
     }
     double d0, omd0, d1, d2, d3;
     const double XY = X + Y;
@@ -710,16 +717,19 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         d2 = et * c2;
         d3 = et * c3;
     } else {
-        const double x = sqrt(X), y = sqrt(Y);
+        // x = sqrt X and 1/x from one reciprocal square root (same for y);
+        // below 1e-200 the invariant is taken as 0 (x < 1e-100 changes no term)
+        const double rX = X > 1e-200 ? rsqrt_fast(X) : 0.0, rY = Y > 1e-200 ? rsqrt_fast(Y) : 0.0;
+        const double x = X * rX, y = Y * rY;
         // u = e^((x - tau)/2), v = e^(-(x + tau)/2): e^(x-tau) = u^2,
         // e^(-x-tau) = v^2, e^-tau = u v
         const double u = exp(0.5 * (x - tau)), v = exp(-0.5 * (x + tau));
         const double ep = u * u, em = v * v, et = u * v;
         const double ch = 0.5 * (ep + em);                              // e^-tau cosh x
-        const double shx = (x > 1e-8) ? 0.5 * (ep - em) * rcp_fast(x) : et;  // e^-tau sinh x / x
+        const double shx = (x > 1e-8) ? 0.5 * (ep - em) * rX : et;  // e^-tau sinh x / x
         double sy, cy;
         sincos(y, &sy, &cy);
-        const double syy = (y > 1e-8) ? sy * rcp_fast(y) : 1.0;
+        const double syy = (y > 1e-8) ? sy * rY : 1.0;
         const double iXY = rcp_fast(XY);
         d0 = (Y * ch + X * et * cy) * iXY;
         d1 = (Y * shx + X * et * syy) * iXY;
@@ -728,7 +738,7 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         // e^-tau (1 - c0) = (2 X e^-tau sin^2(y/2) - 2 Y (e^-tau/2 sinh(x/2))^2) / (X + Y),
         // sin^2(y/2) = sin^2 y / (2 (1 + cos y)) (cos y > 0) or (1 - cos y) / 2
         const double qh = 0.5 * (u - v);
-        const double s2h = (cy > 0.0) ? sy * sy / (2.0 * (1.0 + cy)) : 0.5 * (1.0 - cy);
+        const double s2h = (cy > 0.0) ? 0.5 * sy * sy * rcp_fast(1.0 + cy) : 0.5 * (1.0 - cy);
         omd0 = -expm1(-tau) + 2.0 * (X * et * s2h - Y * qh * qh) * iXY;
     }
     double D[4] = {S[0] - Seq, S[1], S[2], S[3]};
@@ -858,10 +868,10 @@ KRT_HD void fluid_legs(const Metric& g, const double u[4], const double K[4], co
         for (int k = 0; k < 4; ++k) v[k] = b[k] + bu * u[k] - b3 * e3[k];
     }
     const double bb = dot(g, b, b);
-    const double bn = bb > 0.0 ? sqrt(bb) : 0.0;
     double vv = dot(g, v, v);
-    double vn = vv > 0.0 ? sqrt(vv) : 0.0;
-    if (!(bn > 0.0) || !(vn >= 1e-10 * bn)) {
+    // |v| >= 1e-10 |b| tested in squares (no square roots on the common path)
+    if (!(bb > 0.0) || !(vv >= 1e-20 * bb)) {
+        double vn;
         for (int c = 0; c < 2; ++c) {
             const int dir = (c == 0) ? 2 : 1;
             const double cn = sqrt(dir == 2 ? g.hh : g.rr);
@@ -872,7 +882,7 @@ KRT_HD void fluid_legs(const Metric& g, const double u[4], const double K[4], co
             if (vn >= 1e-10 * cn) break;
         }
     }
-    const double iv = vv > 0.0 ? rsqrt_fast(vv) : 1.0 / vn;
+    const double iv = vv > 0.0 ? rsqrt_fast(vv) : __builtin_inf();
     for (int k = 0; k < 4; ++k) e2[k] = v[k] * iv;
     lower(g, e2, l2);
     // e1_nu from the Levi-Civita tensor, sqrt(-g) = Sigma sin(theta)

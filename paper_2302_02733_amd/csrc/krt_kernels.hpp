@@ -251,6 +251,8 @@ KRT_HD void launder_transfer(TraceArgs& L) {
         L.adaf.T0 = opaque(L.adaf.T0);
         L.adaf.beta = opaque(L.adaf.beta);
         L.adaf.h = opaque(L.adaf.h);
+        L.adaf.ibeta = opaque(L.adaf.ibeta);
+        L.adaf.i2h2 = opaque(L.adaf.i2h2);
         L.adaf.risco = opaque(L.adaf.risco);
     }
 }
