@@ -355,9 +355,10 @@ struct AdafDesc {
 KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const Metric& g,
                         Plasma& p) {
     const double c = g.c;
-    const double sr = sqrt(r);
-    const double ir = rcp_fast(r);
-    p.ne = ad.n0 * rcp_fast(r * sr) * exp(-c * c * ad.i2h2);
+    // r^(1/2), 1/r and r^(-3/2) from one reciprocal square root (r > 1)
+    const double irs = rsqrt_fast(r);
+    const double sr = r * irs, ir = irs * irs;
+    p.ne = ad.n0 * (ir * irs) * exp(-c * c * ad.i2h2);
     p.thetae = (kKB / (kME * kC * kC)) * ad.T0 * ir;
     p.B = sqrt((8.0 * kPi * kMP * kC * kC / 6.0) * p.ne * ir * ad.ibeta);
     double Om = 0.0, norm = 1.0;
@@ -590,7 +591,10 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     for (int k = 0; k < 8; ++k) out[k] = 0.0;
     if (!(ne > 0.0) || !(thetae > 0.0) || !(B > 0.0) || !(nu > 0.0)) return 0.0;
     cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
-    const double sth = sqrt(1.0 - cth * cth);
+    // sin(theta_B) and its reciprocal from one reciprocal square root
+    const double s2th = 1.0 - cth * cth;
+    const double isth = s2th > 1e-200 ? rsqrt_fast(s2th) : 0.0;
+    const double sth = s2th * isth;
     const double nuB = kNuBPerB * B;
     const double iTh = rcp_fast(thetae);
     double k0k2, k1k2;
@@ -615,7 +619,7 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     double jI = pre * II;
     double jQ = pre * IQ;
     // j_V = 2 ne e^2 nu cot(theta_B) IV / (3 sqrt3 c Theta^3) = pre (4/3) cot(theta_B) IV / Theta
-    double jV = pre * (4.0 / 3.0) * (cth * rcp_fast(sth)) * iTh * IV;
+    double jV = pre * (4.0 / 3.0) * (cth * isth) * iTh * IV;
     // clamp |j_P| <= j_I, compared in squares where they stay normal numbers
     // (j_I in 1e-140..1e140, |j_Q|, |j_V| below 1e10 j_I); hypot elsewhere
     const bool sq = jI > 1e-140 && jI < 1e140;
@@ -628,7 +632,7 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     out[1] = jQ;
     out[2] = jV;
     const double em1 = expm1(kHnuOverTheta * nu * iTh);
-    const double seq = kSrcFac / em1;
+    const double seq = kSrcFac * rcp_fast(em1);
     const double Bnu = seq * nu * nu * nu;
     if (jI > 0.0 && Bnu > 0.0) {
         const double iB = em1 * (1.0 / kSrcFac) * inu2 * inu;   // 1 / B_nu
