@@ -606,9 +606,15 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     out[6] = 0.5 * kRhoVFac * ne * nuB * nuB * sth * sth * inu2 * inu * (k1k2 + 6.0 * thetae);
 
     const double nuc = 1.5 * nuB * sth * thetae * thetae;
-    const double x13 = cbrt(nu * rcp_fast(nuc));
-    const double xm13 = rcp_fast(x13);
+    // x^(-1/3) from the reciprocal cube root, x^(1/3) = x x^(-2/3)
+    const double xx = nu * rcp_fast(nuc);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double xm13 = rcbrt(xx);
+#else
+    const double xm13 = 1.0 / cbrt(xx);
+#endif
     const double xm23 = xm13 * xm13;
+    const double x13 = xx * xm23;
     const double ex = exp(-1.8899 * x13);
     const double II = 2.5651 * (1.0 + 1.92 * xm13 + 0.9977 * xm23) * ex;
     const double IQ = 2.5651 * (1.0 + 0.93193 * xm13 + 0.499873 * xm23) * ex;
