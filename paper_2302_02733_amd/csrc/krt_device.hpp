@@ -344,6 +344,7 @@ KRT_HD void screen_legs(const CameraDesc& cd, const Metric& g, double alpha, dou
 struct Plasma {
     double ne, thetae, B;
     double u[4], b[4];
+    double bb;   // b.b (the model forms it; the transfer and the tetrad reuse it)
 };
 
 struct AdafDesc {
@@ -384,6 +385,7 @@ KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const 
     p.b[1] = 0.0;
     p.b[2] = 0.0;
     p.b[3] = sc * (1.0 + uph * p.u[3]);
+    p.bb = p.B * p.B;   // b.b = B^2 by construction
     return true;
 }
 
@@ -494,6 +496,7 @@ KRT_HD bool snapshot_plasma(const SnapDesc& s, double a, double m, double r, dou
     p.b[2] = (Bv[2] + bt * p.u[2]) * iut;
     p.b[3] = (Bv[3] + bt * p.u[3]) * iut;
     const double bsq = dot(g, p.b, p.b);
+    p.bb = bsq;
     p.B = sqrt(bsq > 0.0 ? bsq : 0.0) * s.B_unit;
     p.ne = rho * s.rho_unit / (kMP + kME);
     double thetae = 0.0;
@@ -860,7 +863,7 @@ KRT_HD double det3(double a0, double a1, double a2, double b0, double b1, double
 }
 
 KRT_HD void fluid_legs(const Metric& g, const double u[4], const double K[4], const double b[4],
-                       double Ku, double e1[4], double l1[4], double e2[4], double l2[4]) {
+                       double bb, double Ku, double e1[4], double l1[4], double e2[4], double l2[4]) {
     double e3[4], l3[4], ul[4];
     for (int k = 0; k < 4; ++k) e3[k] = K[k] + Ku * u[k];
     lower(g, e3, l3);
@@ -877,7 +880,6 @@ KRT_HD void fluid_legs(const Metric& g, const double u[4], const double K[4], co
         const double b3 = b[0] * l3[0] + b[1] * l3[1] + b[2] * l3[2] + b[3] * l3[3];
         for (int k = 0; k < 4; ++k) v[k] = b[k] + bu * u[k] - b3 * e3[k];
     }
-    const double bb = dot(g, b, b);
     double vv = dot(g, v, v);
     // |v| >= 1e-10 |b| tested in squares (no square roots on the common path)
     if (!(bb > 0.0) || !(vv >= 1e-20 * bb)) {

@@ -325,7 +325,7 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
         lower(g, K, Kl);
         const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
         const double nu = A.cam.freq * (-Ku);
-        const double bb = dot(g, p.b, p.b);
+        const double bb = p.bb;
         const double cth =
             bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) * rsqrt_fast(bb) *
                            rcp_fast(-Ku)
@@ -337,7 +337,7 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
         if (c[3] != 0.0 || c[4] != 0.0 || c[5] != 0.0 || c[6] != 0.0 || c[7] != 0.0) {
             const double fac = A.fac0 * nu;
             double e1[4], l1[4], e2[4], l2[4];
-            fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+            fluid_legs(g, p.u, K, p.b, bb, Ku, e1, l1, e2, l2);
             double S[4];
             coh_project(N, l1, l2, S);
             mueller_thermal(seq, fac * c[3], fac * c[4], fac * c[5], fac * c[6], fac * c[7],
@@ -379,7 +379,7 @@ KRT_HD bool kappa_point(const TraceArgs& A, const double pt[8], Plasma& p, doubl
     lower(g, K, Kl);
     const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
     nu = A.cam.freq * (-Ku);
-    const double bb = dot(g, p.b, p.b);
+    const double bb = p.bb;
     cth = bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
     return true;
 }
@@ -424,7 +424,7 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
         lower(g, K, Kl);
         const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
         const double nu = A.cam.freq * (-Ku);
-        const double bb = dot(g, p.b, p.b);
+        const double bb = p.bb;
         const double cth =
             bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
         double X, sth;
@@ -445,7 +445,7 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
                 const double fa = A.fac0 * nu;
                 const double fj = A.fac0 / (nu * nu);
                 double e1[4], l1[4], e2[4], l2[4];
-                fluid_legs(g, p.u, K, p.b, Ku, e1, l1, e2, l2);
+                fluid_legs(g, p.u, K, p.b, bb, Ku, e1, l1, e2, l2);
                 double S[4];
                 coh_project(N, l1, l2, S);
                 mueller_general(fj * c[0], fj * c[1], fj * c[2], fa * c[3], fa * c[4], fa * c[5], fa * c[6],
