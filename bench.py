@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 # rocprofv3 FP64 VALU instruction counters on a divergence-free launch
 # (bench.py --flop-probe, every lane tracing the same ray), 64 lanes per wave
 # instruction.
-FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "2947.5"))
+FLOPS_PER_RAY_STEP = float(os.environ.get("KRT_FLOPS_PER_RAY_STEP", "2925.5"))
 # Same for the FP32-operator transfer (FP64 plus FP32 VALU operations; both run
 # at the same per-lane rate without packed FP32).
 FLOPS_PER_RAY_STEP_F32 = 2854.5
