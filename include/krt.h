@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 4
+#define KRT_ABI_VERSION 5
 
 typedef enum {
     KRT_OK = 0,
@@ -123,7 +123,9 @@ typedef struct {
     double R_high, R_low;
     double sigma_cut;    /* no emission where b.b/rho > sigma_cut             */
     double r_emit_max;   /* no emission beyond this radius                    */
-    int32_t layout;      /* 0: [n1][n2][n3][8] (rho, u, U1..3, B1..3)         */
+    int32_t layout;      /* 0: [n1][n2][n3][8] (the eight fields of a cell
+                            together); 1: [8][n1][n2][n3] (one array per
+                            field); field order rho, u, U1..3, B1..3          */
 } krt_snapshot_desc;
 
 /* Counters of one krt_trace call. */
@@ -148,8 +150,17 @@ typedef struct {
 /* Version of this ABI (KRT_ABI_VERSION). */
 int krt_abi_version(void);
 
+/* The calls below follow the paper's problem statement (Sec. 2.1): the
+ * inputs of one image are the model (semianalytic or GRMHD arrays), the
+ * mass-accretion-rate scale, the electron-temperature prescription, the spin,
+ * the viewing angle, the observing frequency, the field of view and the
+ * resolution, and the step parameter of the geodesic integration (Sec. 2.2);
+ * the output is one Stokes I, Q, U, V image (Table 1 caption). */
+
 /* Creates a context on HIP device `device` (which becomes current for the
- * calling thread) and builds the library's constant tables there.
+ * calling thread) and builds the library's constant tables there (the
+ * Bessel-function ratios of the thermal rotativities, Sec. 2.1 Faraday
+ * effects).
  * *out receives the context.  Errors: KRT_E_INVAL (bad device or NULL out),
  * KRT_E_NOMEM, KRT_E_HIP. */
 krt_status krt_create(int device, krt_ctx** out);
@@ -162,21 +173,29 @@ krt_status krt_destroy(krt_ctx* ctx);
  * caller keeps ownership and must keep the stream alive. */
 krt_status krt_set_stream(krt_ctx* ctx, void* hip_stream);
 
-/* Sets the physical units (default: none; krt_trace needs them). */
+/* Sets the physical units (default: none; krt_trace needs them): the mass
+ * sets the length unit L = G M / c^2 of the path and, with the distance, the
+ * flux scale of the image (Sec. 2.1, mass-accretion-rate scaling).  Errors:
+ * KRT_E_INVAL (NULL, wrong struct_size, non-finite or non-positive). */
 krt_status krt_set_units(krt_ctx* ctx, const krt_units* units);
 
-/* Selects the analytic ADAF model with these parameters. */
+/* Selects the analytic ADAF model with these parameters (Sec. 2.1: plasma
+ * of a semianalytic model computed at every step along the geodesic).
+ * Errors: KRT_E_INVAL (bad struct or values), KRT_E_UNSUPPORTED (field
+ * geometry other than toroidal). */
 krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* adaf);
 
 /* Element types of snapshot primitives. */
 enum { KRT_DTYPE_F64 = 0, KRT_DTYPE_F32 = 1 };
 
-/* Selects the snapshot model.  d_prims (device memory, layout per desc,
+/* Selects the snapshot model (Sec. 2.1: plasma of a GRMHD model read from
+ * precomputed 3D arrays and interpolated at every step).  d_prims (device
+ * memory, layout per desc,
  * element type KRT_DTYPE_F64 or KRT_DTYPE_F32: the FP32 copy halves the
  * gather traffic and is read by both transfer precisions) is borrowed until
  * the model is replaced or the context is destroyed; the caller must keep it
  * alive and unchanged meanwhile.  Errors: KRT_E_INVAL, KRT_E_UNSUPPORTED
- * (other dtype or layout). */
+ * (dtype other than KRT_DTYPE_F64 / KRT_DTYPE_F32, layout other than 0 or 1). */
 krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc,
                                   const void* d_prims, int dtype);
 
@@ -192,8 +211,11 @@ krt_status krt_set_precision(krt_ctx* ctx, int precision);
 
 /* ---- the hot path ---- */
 
-/* Traces the whole image: per pixel, camera launch, backward geodesic (stored),
- * forward polarized transfer.  d_stokes: [4][ny][nx] FP64, Stokes I, Q, U, V
+/* Traces the whole image (Sec. 2.1): per pixel, camera launch, backward null
+ * geodesic with the eps-controlled adaptive step (stored), then the covariant
+ * polarized transfer of the coherency matrix forward along the stored path
+ * with plasma, emission, absorption and Faraday coefficients at every point
+ * (Sec. 2.1, Sec. 2.2: the CPU code's stored-path scheme).  d_stokes: [4][ny][nx] FP64, Stokes I, Q, U, V
  * in erg s^-1 cm^-2 sr^-1 Hz^-1 at the camera.  d_status: [ny][nx] uint8
  * KRT_RAY_* (may be NULL).  Asynchronous; when out_stats is non-NULL the call
  * synchronises the stream and fills it.  Errors: KRT_E_INVAL, KRT_E_STATE
@@ -202,7 +224,7 @@ krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint
                      krt_stats* out_stats);
 
 /* As krt_trace, and also writes the number of geodesic steps of every ray to
- * d_nsteps ([ny][nx] int32, may be NULL). */
+ * d_nsteps ([ny][nx] int32, may be NULL).  Same errors as krt_trace. */
 krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes,
                            uint8_t* d_status, int32_t* d_nsteps, krt_stats* out_stats);
 
@@ -272,7 +294,9 @@ krt_status krt_autotune(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups,
                         const krt_instance* inst, int32_t ninst, const char* cache_path,
                         krt_launch_config* out_cfg);
 
-/* Image reduction: total flux densities F_S = 1e23 dOmega sum_ij S_ij in Jy,
+/* Image reduction of one Stokes I, Q, U, V image (Table 1 caption; Fig. 1
+ * compares images of one model across resolutions): total flux densities
+ * F_S = 1e23 dOmega sum_ij S_ij in Jy,
  * dOmega = (fov_x L / (nx D)) (fov_y L / (ny D)), L = G M / c^2, with
  * compensated summation, and the maximum of Stokes I.  d_stokes as written by
  * krt_trace for the same camera.  Synchronises the stream.  Errors:
@@ -280,39 +304,55 @@ krt_status krt_autotune(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups,
 krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam,
                       double out_flux_jy[4], double* out_imax);
 
-/* Message of the last error on this context (never NULL). */
+/* Message of the last error on this context (never NULL; owned by the
+ * context, valid until its next call). */
 const char* krt_last_error(const krt_ctx* ctx);
 
 /* ---- host-only checks (no device needed) ---- */
 
-/* Validates a camera without a context: KRT_OK or KRT_E_INVAL with a message
- * copied into msg (msg_len bytes, may be 0). */
+/* Validates a camera (Sec. 2.1 camera parameters, Sec. 2.2 step parameter)
+ * without a context: KRT_OK or KRT_E_INVAL with a message copied into msg
+ * (msg_len bytes, may be 0). */
 krt_status krt_check_camera(const krt_camera* cam, char* msg, size_t msg_len);
 
 /* ---- component hooks (same ABI; used by the parity tests) ---- */
 
-/* Geodesic phase only, for every pixel: d_end_state [ny][nx][8] receives the
- * last stored point (r, theta, phi, K^t, K^r, K^theta, K^phi, dlam),
- * d_nsteps [ny][nx] the step count, d_status [ny][nx] the status. */
+/* Geodesic phase only (Sec. 2.1: a null geodesic per pixel from the camera,
+ * adaptive step set by eps), for every pixel: d_end_state [ny][nx][8]
+ * receives the last stored point (r, theta, phi, K^t, K^r, K^theta, K^phi,
+ * dlam), d_nsteps [ny][nx] the step count, d_status [ny][nx] the status, and
+ * d_invariant_drift [ny][nx][4] (may be NULL) the change between the camera
+ * and the last point of the constants of the motion E = -K_t, L = K_phi and
+ * Carter's Q = K_theta^2 + cos^2(theta) (L^2/sin^2(theta) - a^2 E^2), and the
+ * null condition g(K, K) / (K^t)^2 at the last point (zero at the camera up
+ * to round-off), all exact constants of the continuous geodesic, so their
+ * values measure the integrator's truncation.  d_end_state is required, the
+ * other outputs may be NULL.  Asynchronous.  Errors: KRT_E_INVAL. */
 krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_state,
-                             int32_t* d_nsteps, uint8_t* d_status);
+                             int32_t* d_nsteps, uint8_t* d_status, double* d_invariant_drift);
 
-/* Plasma of the current model at n points: d_X [n][3] = (r, theta, phi) with
- * spin a and mass factor m; d_out [n][12] = (n_e, Theta_e, B, u^0..3, b^0..3,
- * valid).  Needs units for the snapshot model. */
+/* Plasma of the current model at n points (Sec. 2.1: plasma quantities at
+ * every step): d_X [n][3] = (r, theta, phi) with spin a and mass factor m;
+ * d_out [n][12] = (n_e, Theta_e, B, u^0..3, b^0..3, valid).  a and m are
+ * arguments (not a camera) because the hook evaluates a model without a ray.
+ * Needs units for the snapshot model.  Errors: KRT_E_INVAL, KRT_E_STATE. */
 krt_status krt_plasma_eval(krt_ctx* ctx, int64_t n, double a, int32_t mass_factor,
                            const double* d_X, double* d_out);
 
-/* Fluid-frame thermal coefficients at n points: d_in [n][5] = (n_e, Theta_e,
+/* Fluid-frame thermal coefficients at n points (Sec. 2.1: synchrotron
+ * emission, self-absorption, Faraday rotation and conversion): d_in [n][5] = (n_e, Theta_e,
  * B, nu, cos theta_B); d_out [n][8] = (j_I, j_Q, j_V, alpha_I, alpha_Q,
  * alpha_V, rho_Q, rho_V), cgs. */
 krt_status krt_coeffs(krt_ctx* ctx, int64_t n, const double* d_in, double* d_out);
 
-/* Bessel-function ratios at n arguments: d_out [n][2] = (K0/K2, K1/K2). */
+/* Bessel-function ratios at n arguments: d_out [n][2] = (K0/K2, K1/K2)
+ * (the thermal Faraday rotativities of Sec. 2.1). */
 krt_status krt_bessel_ratios(krt_ctx* ctx, int64_t n, const double* d_x, double* d_out);
 
-/* Constant-coefficient polarized update over w at n points, for thermal
- * (Kirchhoff) coefficients: d_coef [n][6] = (S_eq, A_I, A_Q, A_V, R_Q, R_V),
+/* Constant-coefficient polarized update over w at n points (one step of the
+ * polarized transfer of Sec. 2.1), for thermal (Kirchhoff) coefficients,
+ * which is the form the thermal image uses (the general emissivity is
+ * krt_mueller_general): d_coef [n][6] = (S_eq, A_I, A_Q, A_V, R_Q, R_V),
  * so that the emission is J = S_eq (A_I, A_Q, 0, A_V); d_S [n][4] in,
  * d_out [n][4] out. */
 krt_status krt_mueller_step(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S,

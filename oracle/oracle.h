@@ -113,7 +113,9 @@ int or_trace_ray(const or_camera* cam, double alpha, double beta, int32_t cap,
                  double* path, int32_t* n_end, int32_t* status);
 /* Plasma at a point: out = ne, Thetae, B, u^0..3, b^0..3 (11 doubles);
  * L_cm = G M / c^2 is the length unit (used by the snapshot's code units).
- * Returns 1 when the fluid four-velocity is valid, 0 otherwise. */
+ * Returns 1 when the fluid four-velocity is valid, 0 otherwise, and 2 when
+ * a snapshot's gathered primitives are not finite at a point within the
+ * emission radius (the transfer then poisons the ray: status NONFINITE). */
 int or_plasma(const or_model* model, const or_snapshot* snap, double a, double m,
               double r, double th, double ph, double L_cm, double out[11]);
 /* Fluid-frame thermal coefficients (cgs): out = j_I j_Q j_V a_I a_Q a_V r_Q r_V. */

@@ -151,6 +151,10 @@ static int snapshot(const or_snapshot* s, double a, double m, double r, double t
     double P[8];
     interp_prims(s, x1, x2, x3, P);
     double rho = P[0], uu = P[1];
+    /* a non-finite value among the gathered primitives where the snapshot
+     * emits: reported (2), and the transfer poisons the ray with it */
+    if (r <= s->r_emit_max && !std::isfinite(P[0] + P[1] + P[2] + P[3] + P[4] + P[5] + P[6] + P[7]))
+        return 2;
 
     /* metric in grid coordinates: g_mks = J^T g_ks J, J = diag(1, r, dtheta/dx2, 1) */
     Mat4 gks, g, gi;

@@ -29,6 +29,7 @@
  *  - camera output: N projected on the pixel's screen legs, times nu_obs^3.
  */
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include "oracle_internal.h"
 
@@ -241,7 +242,15 @@ static void radiative_update(const or_camera* cam, double L_cm, const or_model* 
     Mat4 g;
     metric(a, m, r, th, g);
     Plasma p;
-    if (!plasma(model, snap, a, m, r, th, ph, L_cm, &p)) return;  /* no valid fluid frame */
+    const int pk = plasma(model, snap, a, m, r, th, ph, L_cm, &p);
+    if (pk == 2) {
+        /* non-finite snapshot data at an emitting point: the ray's Stokes
+         * vector becomes non-finite, and the pixel is written as zeros with
+         * status NONFINITE */
+        N[0][0] = cplx(std::numeric_limits<double>::quiet_NaN(), 0.0);
+        return;
+    }
+    if (!pk) return;  /* no valid fluid frame */
 
     double Ku = dot(g, K, p.u);
     double nu = cam->freq_hz * (-Ku);

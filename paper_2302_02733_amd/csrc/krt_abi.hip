@@ -27,6 +27,9 @@ struct krt_ctx {
     krt_snapshot_desc snap{};
     const double* snap_prims = nullptr;
     const float* snap_prims_f = nullptr;
+    // layout-1 snapshots are read through a library-owned layout-0 copy
+    void* snap_copy = nullptr;
+    size_t snap_copy_bytes = 0;
     int precision = KRT_PRECISION_FP64;
     double* btab = nullptr;
     // wave-synchronous path store
@@ -731,6 +734,7 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->btab) (void)hipFree(ctx->btab);
     if (ctx->syntab) (void)hipFree(ctx->syntab);
     if (ctx->tile_order) (void)hipFree(ctx->tile_order);
+    if (ctx->snap_copy) (void)hipFree(ctx->snap_copy);
     if (ctx->mlp_P) (void)hipFree(ctx->mlp_P);
     if (ctx->mlp_m) (void)hipFree(ctx->mlp_m);
     if (ctx->mlp_v) (void)hipFree(ctx->mlp_v);
@@ -778,7 +782,8 @@ krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, c
     if (!d_prims) return fail(ctx, KRT_E_INVAL, "d_prims is NULL");
     if (dtype != KRT_DTYPE_F64 && dtype != KRT_DTYPE_F32)
         return fail(ctx, KRT_E_UNSUPPORTED, "dtype must be KRT_DTYPE_F64 or KRT_DTYPE_F32");
-    if (desc->layout != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only layout 0 is supported");
+    if (desc->layout != 0 && desc->layout != 1)
+        return fail(ctx, KRT_E_UNSUPPORTED, "layout must be 0 ([n1][n2][n3][8]) or 1 ([8][n1][n2][n3])");
     const krt_snapshot_desc& d = *desc;
     if (d.n1 < 2 || d.n2 < 2 || d.n3 < 1) return fail(ctx, KRT_E_INVAL, "grid needs n1, n2 >= 2 and n3 >= 1");
     if ((int64_t)d.n1 * d.n2 * d.n3 > ((int64_t)1 << 31) / 8) return fail(ctx, KRT_E_INVAL, "grid too large");
@@ -788,6 +793,35 @@ krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, c
     if (!(d.dx1 > 0.0 && d.dx2 > 0.0 && d.dx3 > 0.0)) return fail(ctx, KRT_E_INVAL, "cell sizes must be > 0");
     if (!(d.M_unit_g > 0.0) || !(d.gamma_ad > 1.0)) return fail(ctx, KRT_E_INVAL, "need M_unit > 0, gamma_ad > 1");
     if (!(d.hslope > 0.0 && d.hslope <= 1.0)) return fail(ctx, KRT_E_INVAL, "hslope must be in (0, 1]");
+    if (d.layout == 1) {
+        // one transpose into the library's copy in the gather's layout (the
+        // copy is read instead of d_prims from now on)
+        const size_t ncell = (size_t)d.n1 * d.n2 * d.n3;
+        const size_t esz = dtype == KRT_DTYPE_F64 ? sizeof(double) : sizeof(float);
+        const size_t bytes = ncell * 8 * esz;
+        KRT_HIP(ctx, hipSetDevice(ctx->device));
+        if (ctx->snap_copy_bytes < bytes) {
+            KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->snap_copy) KRT_HIP(ctx, hipFree(ctx->snap_copy));
+            ctx->snap_copy = nullptr;
+            ctx->snap_copy_bytes = 0;
+            if (hipMalloc(&ctx->snap_copy, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->snap_copy = nullptr;
+                return fail(ctx, KRT_E_NOMEM, "cannot allocate the snapshot copy for layout 1");
+            }
+            ctx->snap_copy_bytes = bytes;
+        }
+        const dim3 grid((unsigned)((ncell + 63) / 64));
+        if (dtype == KRT_DTYPE_F64)
+            hipLaunchKernelGGL(snapshot_to_cells<double>, grid, dim3(256), 0, ctx->stream,
+                               static_cast<const double*>(d_prims), static_cast<double*>(ctx->snap_copy), ncell);
+        else
+            hipLaunchKernelGGL(snapshot_to_cells<float>, grid, dim3(256), 0, ctx->stream,
+                               static_cast<const float*>(d_prims), static_cast<float*>(ctx->snap_copy), ncell);
+        KRT_HIP(ctx, hipGetLastError());
+        d_prims = ctx->snap_copy;
+    }
     ctx->snap = d;
     ctx->snap_prims = dtype == KRT_DTYPE_F64 ? static_cast<const double*>(d_prims) : nullptr;
     ctx->snap_prims_f = dtype == KRT_DTYPE_F32 ? static_cast<const float*>(d_prims) : nullptr;
@@ -812,11 +846,9 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     const size_t npix = (size_t)cam->nx * cam->ny;
     const int el = ctx->electrons;
     const bool f32 = el == KRT_ELECTRONS_THERMAL && ctx->precision == KRT_PRECISION_FP32_TRANSFER;
-    if (el != KRT_ELECTRONS_THERMAL) {
-        if ((st = ensure_syntab(ctx)) != KRT_OK) return st;
-        if (el == KRT_ELECTRONS_KAPPA_SURROGATE && !ctx->mlp_ready)
-            return fail(ctx, KRT_E_STATE, "kappa surrogate selected but no surrogate parameters set");
-    }
+    if (el == KRT_ELECTRONS_KAPPA_SURROGATE && !ctx->mlp_ready)
+        return fail(ctx, KRT_E_STATE, "kappa surrogate selected but no surrogate parameters set");
+    if (el != KRT_ELECTRONS_THERMAL && (st = ensure_syntab(ctx)) != KRT_OK) return st;
     if (el == KRT_ELECTRONS_KAPPA_SURROGATE) st = ensure_pool<kModeKapMlp>(ctx);
     else if (el == KRT_ELECTRONS_KAPPA_EXACT) st = ensure_pool<kModeKapExact>(ctx);
     else st = f32 ? ensure_pool<kModeF32>(ctx) : ensure_pool<kModeF64>(ctx);
@@ -1122,7 +1154,7 @@ krt_status krt_autotune(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups,
 }
 
 krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_state,
-                             int32_t* d_nsteps, uint8_t* d_status) {
+                             int32_t* d_nsteps, uint8_t* d_status, double* d_invariant_drift) {
     if (!ctx) return KRT_E_INVAL;
     const std::string m = check_camera(cam);
     if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
@@ -1132,6 +1164,7 @@ krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_
     A.end_state = d_end_state;
     A.nsteps = d_nsteps;
     A.status = d_status;
+    A.drift = d_invariant_drift;
     int per_cu = 0;
     KRT_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, trace_waves<kModeGeo>, 256, 0));
     const int blocks = (per_cu < 1 ? 1 : per_cu) * ctx->cu_count;

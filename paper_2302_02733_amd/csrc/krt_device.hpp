@@ -459,8 +459,10 @@ KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, 
 // b^i = (B^i + b^t u^i) / u^t; T_i/T_e = (R_high beta^2 + R_low)/(1 + beta^2)
 // with beta = (gamma_ad - 1) u / (b.b/2); no emission (n_e = 0) where
 // b.b/rho > sigma_cut or r > r_emit_max.
-KRT_HD bool snapshot_plasma(const SnapDesc& s, double a, double m, double r, double th, double ph,
-                            const Metric& g, Plasma& p) {
+// Returns 1, or 2 when the gathered primitives are not finite (the caller
+// poisons the ray: its pixel is written as NONFINITE).
+KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, double th, double ph,
+                           const Metric& g, Plasma& p) {
     const double x1 = log(r);
     double x2 = th * (1.0 / kPi);
     const double hh = 0.5 * (1.0 - s.h);
@@ -475,6 +477,7 @@ KRT_HD bool snapshot_plasma(const SnapDesc& s, double a, double m, double r, dou
     }
     double P[8];
     snapshot_interp(s, x1, x2, ph, P);
+    if (!is_finite(P[0] + P[1] + P[2] + P[3] + P[4] + P[5] + P[6] + P[7])) return 2;
     const double rho = P[0], uu = P[1];
     const double J2 = kPi * (1.0 + (1.0 - s.h) * cos(2.0 * kPi * x2));
     const double U[4] = {0.0, P[2] * r, P[3] * J2, P[4]};
@@ -510,7 +513,7 @@ KRT_HD bool snapshot_plasma(const SnapDesc& s, double a, double m, double r, dou
     if (!(rho > 0.0) || bsq / rho > s.sigma_cut || r > s.rmax) p.ne = 0.0;
     (void)a;
     (void)m;
-    return true;
+    return 1;
 }
 
 // ---------------------------------------------------------------------------

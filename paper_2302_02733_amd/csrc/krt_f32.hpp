@@ -226,9 +226,11 @@ KRT_HD void snapshot_interp_f(const P* prims, int n1, int n2, int n3, float X0, 
     }
 }
 
+// Returns 1, or 2 when the gathered primitives are not finite (in FP32:
+// values beyond its range count as non-finite).
 template <class P>
-KRT_HD bool snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2, int n3, float r,
-                              float th, float X2, const MetricF& g, PlasmaF& p) {
+KRT_HD int snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2, int n3, float r,
+                             float th, float X2, const MetricF& g, PlasmaF& p) {
     const float x1 = logf(r);
     const float kPif = 3.14159265f;
     float x2 = th * (1.0f / kPif);
@@ -244,6 +246,7 @@ KRT_HD bool snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2
     float Pv[8];
     snapshot_interp_f(prims, n1, n2, n3, (x1 - C.x1s) * C.idx1 - 0.5f, (x2 - C.x2s) * C.idx2 - 0.5f,
                       X2, Pv);
+    if (!(fabsf(Pv[0] + Pv[1] + Pv[2] + Pv[3] + Pv[4] + Pv[5] + Pv[6] + Pv[7]) <= 3.4028235e38f)) return 2;
     const float rho = Pv[0], uu = Pv[1];
     const float J2 = kPif * (1.0f + 2.0f * C.hh * cs2);
     const float U1 = Pv[2] * r, U2 = Pv[3] * J2, U3 = Pv[4];
@@ -275,7 +278,7 @@ KRT_HD bool snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2
     }
     p.thetae = thetae;
     if (!(rho > 0.0f) || bsq / rho > C.sigma_cut || r > C.rmax) p.ne = 0.0f;
-    return true;
+    return 1;
 }
 
 // K0/K2 and K1/K2 of x = 1/Theta_e from the FP32 copy of the Chebyshev table

@@ -77,6 +77,7 @@ struct TraceArgs {
     uint8_t* status;    // [ny][nx] or null
     int32_t* nsteps;    // [ny][nx] or null
     double* end_state;  // geodesic-only mode: [ny][nx][8]
+    double* drift;      // geodesic-only mode: [ny][nx][4] invariant drift, or null
     unsigned long long* counters;  // steps, status[5], max steps, long rays, surrogate / exact points
     // kappa electrons
     double kappa;
@@ -182,6 +183,24 @@ KRT_HD uint8_t stop_test(const TraceArgs& A, const double y[7], double h, int n,
     return kRunning;
 }
 
+// Constants of a Kerr null geodesic (Carter 1968), from the state
+// y = (r, theta, phi, K^t, K^r, K^theta, K^phi): E = -K_t, L = K_phi,
+// Q = K_theta^2 + cos^2(theta) (L^2 / sin^2(theta) - a^2 E^2), and the null
+// condition g(K, K) / (K^t)^2.  The covariant t, theta and phi components
+// are the same in Kerr-Schild and Boyer-Lindquist coordinates.
+KRT_HD void geodesic_invariants(double a, double m, const double y[7], double c[4]) {
+    Metric g;
+    metric_eval(a, m, y[0], y[1], g);
+    const double K[4] = {y[3], y[4], y[5], y[6]};
+    double Kl[4];
+    lower(g, K, Kl);
+    const double E = -Kl[0], L = Kl[3];
+    c[0] = E;
+    c[1] = L;
+    c[2] = Kl[2] * Kl[2] + g.c * g.c * (L * L / (g.s * g.s) - a * a * E * E);
+    c[3] = (K[0] * Kl[0] + K[1] * Kl[1] + K[2] * Kl[2] + K[3] * Kl[3]) / (K[0] * K[0]);
+}
+
 KRT_HD void store_point(double* p, const double y[7], double h) {
     double2* q = reinterpret_cast<double2*>(p);
     q[0] = make_double2(y[0], y[1]);
@@ -277,17 +296,23 @@ struct XferStateF {
     double Dnext;
 };
 
-// Plasma for the radiative update; false where the update leaves N unchanged:
-// no timelike flow, or (snapshot) beyond the emission radius, where n_e = 0
-// makes every coefficient zero.
-KRT_HD bool plasma_at(const TraceArgs& A, double r, double th, double ph, const Metric& g,
-                      Plasma& p) {
+// Plasma for the radiative update: 1 with the plasma in p; 0 where the update
+// leaves N unchanged (no timelike flow, or (snapshot) beyond the emission
+// radius, where n_e = 0 makes every coefficient zero); 2 where the snapshot's
+// gathered primitives are not finite (the ray is poisoned).
+KRT_HD int plasma_at(const TraceArgs& A, double r, double th, double ph, const Metric& g,
+                     Plasma& p) {
     if (A.model == kModelSnapshot) {
-        if (r > A.snap.rmax) return false;
+        if (r > A.snap.rmax) return 0;
         return snapshot_plasma(A.snap, A.cam.a, A.cam.m, r, th, ph, g, p);
     }
-    return adaf_plasma(A.adaf, A.cam.a, A.cam.m, r, g, p);
+    return adaf_plasma(A.adaf, A.cam.a, A.cam.m, r, g, p) ? 1 : 0;
 }
+
+// Quiet NaN that poisons a ray's coherency matrix: non-finite snapshot data at
+// an emitting point make the ray's Stokes vector non-finite, and its pixel is
+// written as zeros with status NONFINITE.
+KRT_HD double poison_nan() { return __builtin_nan(""); }
 
 // Processes stored point n (first: the far end of the path).  On return N
 // holds the coherency matrix at the point after its radiative update.
@@ -320,7 +345,9 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
 
     // radiative update over w_n = (D_n + D_{n+1}) / 2
     Plasma p;
-    if (plasma_at(A, r, th, ph, g, p)) {
+    const int pk = plasma_at(A, r, th, ph, g, p);
+    if (pk == 2) N.R[0] = poison_nan();
+    if (pk == 1) {
         double Kl[4];
         lower(g, K, Kl);
         const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
@@ -367,30 +394,32 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
     }
 }
 
-// Fluid-frame inputs of the kappa coefficients at a stored point: false
-// where the point has no plasma (the update leaves N unchanged).
-KRT_HD bool kappa_point(const TraceArgs& A, const double pt[8], Plasma& p, double& nu, double& cth) {
+// Fluid-frame inputs of the kappa coefficients at a stored point; returns the
+// plasma_at result (1: plasma in p, nu and cth set; 0: none, the update leaves
+// N unchanged; 2: non-finite data, the update poisons the ray).
+KRT_HD int kappa_point(const TraceArgs& A, const double pt[8], Plasma& p, double& nu, double& cth) {
     const double r = pt[0], th = pt[1], ph = pt[2];
     const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
     Metric g;
     metric_eval(A.cam.a, A.cam.m, r, th, g);
-    if (!plasma_at(A, r, th, ph, g, p)) return false;
+    const int pk = plasma_at(A, r, th, ph, g, p);
+    if (pk != 1) return pk;
     double Kl[4];
     lower(g, K, Kl);
     const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
     nu = A.cam.freq * (-Ku);
     const double bb = p.bb;
     cth = bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
-    return true;
+    return 1;
 }
 
 // transfer_point for kappa electrons: the coefficients come from the eight
 // integrals I_in when use_in, else from the exact integrator (counted in
 // n_exact); the update is the general constant-coefficient one.  pre: the
-// plasma at the point when already evaluated (has_pre: it exists).
+// plasma at the point when already evaluated, pre_kind its plasma_at result.
 KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, bool first, XferState& st,
                                  Coh& N, const double* I_in, bool use_in, unsigned& n_exact,
-                                 const Plasma* pre = nullptr, bool has_pre = false) {
+                                 const Plasma* pre = nullptr, int pre_kind = 0) {
     const double r = pt[0], th = pt[1], ph = pt[2];
     const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
     const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
@@ -412,14 +441,15 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
         for (int k = 0; k < 6; ++k) N.I[k] = st.H.I[k] + hh * F.I[k];
     }
     Plasma p;
-    bool have;
+    int pk;
     if (pre) {
-        have = has_pre;
-        if (have) p = *pre;
+        pk = pre_kind;
+        if (pk == 1) p = *pre;
     } else {
-        have = plasma_at(A, r, th, ph, g, p);
+        pk = plasma_at(A, r, th, ph, g, p);
     }
-    if (have) {
+    if (pk == 2) N.R[0] = poison_nan();
+    if (pk == 1) {
         double Kl[4];
         lower(g, K, Kl);
         const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
@@ -517,19 +547,20 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bo
     }
 
     PlasmaF p;
-    bool ok;
+    int pk = 0;
     if (A.model == kModelSnapshot) {
         const SnapDesc& q = A.snap;
         double X2 = (pt[2] - q.x3s) / q.dx3 - 0.5;
         X2 -= q.n3 * floor(X2 / q.n3);
         // no plasma beyond the emission radius (n_e = 0: every coefficient zero)
-        ok = pt[0] <= q.rmax &&
-             (q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
-                        : snapshot_plasma_f(C, q.prims, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p));
+        if (pt[0] <= q.rmax)
+            pk = q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
+                           : snapshot_plasma_f(C, q.prims, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p);
     } else {
-        ok = adaf_plasma_f(C, r, g, p);
+        pk = adaf_plasma_f(C, r, g, p) ? 1 : 0;
     }
-    if (ok) {
+    if (pk == 2) N.R[0] = poison_nan();
+    if (pk == 1) {
         float Kl[4];
         lower_f(g, K, Kl);
         const float Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
@@ -579,8 +610,10 @@ KRT_HD void camera_output(const TraceArgs& A, double alpha, double beta,
     for (int k = 0; k < 4; ++k) S[k] *= nu3;
 }
 
-__device__ __forceinline__ void write_pixel(const TraceArgs& A, int pix, double S[4], uint8_t st,
-                                            int nst) {
+// Writes one pixel; a non-finite Stokes vector is written as zeros with
+// status NONFINITE.  Returns the status written (the one the counters take).
+__device__ __forceinline__ uint8_t write_pixel(const TraceArgs& A, int pix, double S[4], uint8_t st,
+                                               int nst) {
     const bool ok = is_finite(S[0]) && is_finite(S[1]) && is_finite(S[2]) && is_finite(S[3]);
     if (!ok) {
         S[0] = S[1] = S[2] = S[3] = 0.0;
@@ -590,6 +623,7 @@ __device__ __forceinline__ void write_pixel(const TraceArgs& A, int pix, double 
     for (int k = 0; k < 4; ++k) A.stokes[k * np + pix] = S[k];
     if (A.status) A.status[pix] = st;
     if (A.nsteps) A.nsteps[pix] = nst;
+    return st;
 }
 
 // Wave-level accounting of finished rays (one atomic per counter per wave).
@@ -672,7 +706,6 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
         A.overflow_list[k] = pix;
         if (A.overflow_inst) A.overflow_inst[k] = A.inst_id;
     }
-    account(A, valid, st, n);
 
     // ---- transfer: all lanes on the same point index, far end first ----
     const bool xfer = valid && st != kOverflow;
@@ -701,15 +734,16 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
             // surrogate inputs of this lane's point (in-domain points only),
             // the network for the whole wave, then the update
             float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            bool want = false, has = false, fall = false;
+            bool want = false, fall = false;
+            int pk = 0;
             double Xp = 0.0;
             Plasma p;
             if (m <= n_end) {
                 double pt[8];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 double nu, cth, sth;
-                has = kappa_point(A, pt, p, nu, cth);
-                if (has && kappa_frame(p.ne, p.thetae, p.B, nu, cth, Xp, sth)) {
+                pk = kappa_point(A, pt, p, nu, cth);
+                if (pk == 1 && kappa_frame(p.ne, p.thetae, p.B, nu, cth, Xp, sth)) {
                     if (mlp_in_domain(A.kappa, p.thetae, Xp)) {
                         mlp_features(A.kappa, p.thetae, Xp, cth, f);
                         want = true;
@@ -737,7 +771,7 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 n_mlp += want ? 1u : 0u;
                 n_exact += fall ? 1u : 0u;
-                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, has);
+                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, pk);
             }
         } else {
             double pt[8];
@@ -762,13 +796,18 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
         }
     }
     if constexpr (kKappa<kMode>) kappa_account(A, n_mlp, n_exact);
+    uint8_t st_out = st;
     if (xfer) {
         double S[4];
         TraceArgs L = A;
         launder_camera(L.cam);
         camera_output(L, alpha, beta, N, S);
-        write_pixel(A, pix, S, st, n);
+        st_out = write_pixel(A, pix, S, st, n);
     }
+    // counted with the status written (a non-finite Stokes vector turns the
+    // geodesic's status into NONFINITE); overflow rays are counted by the
+    // long-ray kernel
+    account(A, valid, st_out, n);
 }
 
 // Pixel of a lane in tile `tile` of an image with tiles_x tiles per row; a
@@ -929,6 +968,21 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2
                 e[7] = hlast;
                 if (A.status) A.status[pix] = st;
                 if (A.nsteps) A.nsteps[pix] = n;
+                if (A.drift) {
+                    // constants of the motion at the camera (the launch state,
+                    // recomputed) and at the last point
+                    double y0[7], c0[4], c1[4];
+                    CameraDesc C = A.cam;
+                    launder_camera(C);
+                    double X[4], K[4];
+                    camera_launch(C, alpha, beta, X, K);
+                    y0[0] = X[1]; y0[1] = X[2]; y0[2] = X[3];
+                    y0[3] = K[0]; y0[4] = K[1]; y0[5] = K[2]; y0[6] = K[3];
+                    geodesic_invariants(C.a, C.m, y0, c0);
+                    geodesic_invariants(C.a, C.m, y, c1);
+                    double* d = A.drift + (size_t)pix * 4;
+                    for (int k = 0; k < 4; ++k) d[k] = c1[k] - c0[k];
+                }
             }
             account(A, valid, st, n);
         } else {
@@ -1107,10 +1161,10 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         if constexpr (kKappa<kMode>) atomicAdd(&A.counters[9], (unsigned long long)n_exact);
         double S[4];
         camera_output(R, alpha, beta, N, S);
-        write_pixel(R, pix, S, st, n);
+        const uint8_t st_out = write_pixel(R, pix, S, st, n);
         // the wave-synchronous pass counted this ray as overflow; count it now
         atomicAdd(&A.counters[0], (unsigned long long)n);
-        atomicAdd(&A.counters[1 + st], 1ULL);
+        atomicAdd(&A.counters[1 + st_out], 1ULL);
         atomicMax(&A.counters[6], (unsigned long long)n);
     }
 }
@@ -1157,6 +1211,29 @@ __global__ void bessel_table_coefs(const double* vals, double* table) {
     s *= 2.0 / kBesCoef;
     if (j == 0) s *= 0.5;
     table[(size_t)p * 2 * kBesCoef + f * kBesCoef + j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Snapshot layout 1 ([8][ncell], one array per field) to layout 0
+// ([ncell][8], the fields of a cell together, which the gather reads as
+// vectors): 64 cells per block staged through LDS, so that both the reads of
+// each field and the writes of whole cells are coalesced.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void snapshot_to_cells(const T* __restrict__ src, T* __restrict__ dst,
+                                                         size_t ncell) {
+    __shared__ T tile[8][65];
+    const size_t c0 = (size_t)blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;   // 4 groups of 64 threads
+    for (int q = grp; q < 8; q += 4) {
+        const size_t c = c0 + lane;
+        tile[q][lane] = c < ncell ? src[(size_t)q * ncell + c] : T(0);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 512; k += 256) {
+        const size_t c = c0 + k / 8;
+        if (c < ncell) dst[c * 8 + (k % 8)] = tile[k % 8][k / 8];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1226,9 +1303,9 @@ __global__ void hook_plasma(TraceArgs A, int64_t n, double a, double m, const do
     const double r = X[k * 3], th = X[k * 3 + 1], ph = X[k * 3 + 2];
     Metric g;
     metric_eval(a, m, r, th, g);
-    Plasma p;
+    Plasma p{};
     // the model itself (plasma_at also skips points the transfer leaves alone)
-    const bool ok = A.model == kModelSnapshot ? snapshot_plasma(A.snap, a, m, r, th, ph, g, p)
+    const bool ok = A.model == kModelSnapshot ? snapshot_plasma(A.snap, a, m, r, th, ph, g, p) == 1
                                               : adaf_plasma(A.adaf, a, m, r, g, p);
     double* o = out + k * 12;
     o[0] = p.ne; o[1] = p.thetae; o[2] = p.B;

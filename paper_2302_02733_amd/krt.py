@@ -108,7 +108,7 @@ _SIGS = {
                                   ctypes.POINTER(ctypes.c_double)]),
     "krt_last_error": (ctypes.c_char_p, [_P]),
     "krt_check_camera": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_char_p, ctypes.c_size_t]),
-    "krt_geodesic_only": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P]),
+    "krt_geodesic_only": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P, _P]),
     "krt_plasma_eval": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P]),
     "krt_coeffs": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "krt_bessel_ratios": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
@@ -233,13 +233,14 @@ class Context:
         self._check(lib().krt_set_model_adaf(self.h, ctypes.byref(m)))
 
     def set_model_snapshot(self, desc, prims):
-        """desc: snapshot description dict; prims: float64 or float32
-        [n1][n2][n3][8] device tensor, borrowed (keep it alive while the model
-        is in use)."""
+        """desc: snapshot description dict (layout 0 or 1); prims: float64 or
+        float32 device tensor [n1][n2][n3][8] (layout 0) or [8][n1][n2][n3]
+        (layout 1), borrowed (keep it alive while the model is in use)."""
         _dev(prims, self.device)
-        if prims.dtype not in (torch.float64, torch.float32) or \
-                tuple(prims.shape) != (desc["n1"], desc["n2"], desc["n3"], 8):
-            raise ValueError("prims must be float64 or float32 [n1][n2][n3][8]")
+        n = (desc["n1"], desc["n2"], desc["n3"])
+        shape = (8,) + n if desc.get("layout", 0) == 1 else n + (8,)
+        if prims.dtype not in (torch.float64, torch.float32) or tuple(prims.shape) != shape:
+            raise ValueError(f"prims must be float64 or float32 {list(shape)}")
         d = SnapshotDesc()
         d.struct_size = ctypes.sizeof(SnapshotDesc)
         for name, _ in SnapshotDesc._fields_[1:]:
@@ -344,15 +345,18 @@ class Context:
         self._check(lib().krt_reduce(self.h, _ptr(stokes), ctypes.byref(c), flux, ctypes.byref(imax)))
         return list(flux), imax.value
 
-    def geodesic_only(self, cam):
+    def geodesic_only(self, cam, drift=False):
+        """Returns (end state [ny,nx,8], steps [ny,nx], status [ny,nx]) and,
+        with drift=True, also the invariant drift [ny,nx,4] (E, L, Q, null)."""
         nx, ny = cam["nx"], cam["ny"]
         end = torch.empty((ny, nx, 8), dtype=torch.float64, device=self.device)
         ns = torch.empty((ny, nx), dtype=torch.int32, device=self.device)
         st = torch.empty((ny, nx), dtype=torch.uint8, device=self.device)
+        dr = torch.empty((ny, nx, 4), dtype=torch.float64, device=self.device) if drift else None
         c = make_camera(cam)
         self._stream()
-        self._check(lib().krt_geodesic_only(self.h, ctypes.byref(c), _ptr(end), _ptr(ns), _ptr(st)))
-        return end, ns, st
+        self._check(lib().krt_geodesic_only(self.h, ctypes.byref(c), _ptr(end), _ptr(ns), _ptr(st), _ptr(dr)))
+        return (end, ns, st, dr) if drift else (end, ns, st)
 
     def plasma_eval(self, X, a, mass_factor=1):
         X = _dev(X, self.device)

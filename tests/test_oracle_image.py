@@ -24,3 +24,19 @@ def test_total_flux_converges_in_eps():
     ratio = d1 / d2
     assert abs(d2) / fl[2] < 1e-2
     assert 2.0 < ratio < 8.0, (fl, ratio)
+
+
+def test_parity_images_are_realizable():
+    """P12 on the oracle's own parity images (the 64^2 ADAF and the 48^2
+    snapshot, the images the GPU is compared with in full): I >= 0 and
+    I^2 (1 + 1e-12) >= Q^2 + U^2 + V^2 at every pixel."""
+    for name in ("adaf64", "snap48"):
+        w = W.workload(name)
+        snap = None
+        if "snapshot" in w:
+            desc, seed = w["snapshot"]
+            snap = oracle.SnapshotHandle(desc, W.make_snapshot(desc, seed))
+        S, st, ns = oracle.render(w["camera"], w["units"], w["model"], snap=snap)
+        I, Q, U, V = S
+        assert np.all(I >= 0) and I.max() > 0
+        assert np.all(I * I * (1 + 1e-12) >= Q * Q + U * U + V * V), name

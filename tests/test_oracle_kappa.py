@@ -170,3 +170,24 @@ def test_physical_guards():
     cm = oracle.kappa_coefficients(5.0, 1e6, 10.0, 10.0, 230e9, -0.3)
     assert np.allclose(cm[[0, 1, 3, 4, 6]], c[[0, 1, 3, 4, 6]], rtol=1e-14)
     assert np.allclose(cm[[2, 5, 7]], -c[[2, 5, 7]], rtol=1e-14)
+
+
+@pytest.mark.parametrize("kap", [4.0, 6.0])
+def test_rotativities_cold_limit(kap):
+    """A cold kappa plasma (width w -> 0) rotates and converts like a cold
+    electron gas: rho_V -> 2 n e^2 nu_B cos(theta) / (m c nu^2) (the
+    textbook Faraday rotation rate, twice the rotation-measure rate
+    e^3 n B cos(theta) / (2 pi m^2 c^2 nu^2)) and rho_Q -> n e^2 nu_B^2
+    sin^2(theta) / (m c nu^3) (the quadratic birefringence of the
+    Appleton-Hartree indices).  This fixes both rotativity weights at
+    g -> 1 independently of the thermal module; between the cold and the
+    thermal high-frequency limits the kappa weights are a reading."""
+    ne, B, nu = 1e6, 10.0, 230e9
+    nuB = E * B / (2 * math.pi * ME * C)
+    for cth in (0.3, -0.8):
+        s2 = 1 - cth * cth
+        c = oracle.kappa_coefficients(kap, ne, 1e-5, B, nu, cth)
+        rv = 2 * ne * E * E * nuB * cth / (ME * C * nu * nu)
+        rq = ne * E * E * nuB * nuB * s2 / (ME * C * nu ** 3)
+        assert abs(c[7] / rv - 1) < 1e-3, c[7] / rv
+        assert abs(c[6] / rq - 1) < 1e-3, c[6] / rq
