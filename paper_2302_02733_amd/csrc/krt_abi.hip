@@ -13,6 +13,7 @@
 
 #include "krt.h"
 #include "krt_kernels.hpp"
+#include "krt_validate.hpp"
 
 using namespace krt;
 
@@ -103,41 +104,10 @@ krt_status hip_fail(krt_ctx* ctx, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);    \
     } while (0)
 
-bool finite_all(std::initializer_list<double> v) {
-    for (double x : v)
-        if (!std::isfinite(x)) return false;
-    return true;
-}
-
-double horizon(double a, double m) { return m == 0.0 ? 0.0 : m + std::sqrt(m * m - a * a); }
-
-// r_isco of Kerr (Bardeen, Press & Teukolsky 1972), prograde for a > 0.
-double isco(double a) {
-    const double aa = std::fabs(a);
-    const double z1 = 1.0 + std::cbrt(1.0 - aa * aa) * (std::cbrt(1.0 + aa) + std::cbrt(1.0 - aa));
-    const double z2 = std::sqrt(3.0 * aa * aa + z1 * z1);
-    return 3.0 + z2 - (a >= 0.0 ? 1.0 : -1.0) * std::sqrt((3.0 - z1) * (3.0 + z1 + 2.0 * z2));
-}
-
-std::string check_camera(const krt_camera* c) {
-    if (!c) return "camera is NULL";
-    if (c->struct_size != sizeof(krt_camera)) return "camera struct_size mismatch";
-    if (!finite_all({c->a, c->incl_deg, c->phi_deg, c->r_cam, c->fov_x, c->fov_y, c->freq_hz, c->eps}))
-        return "camera has a non-finite field";
-    if (!(std::fabs(c->a) < 1.0)) return "spin must satisfy |a| < 1";
-    if (c->mass_factor != 0 && c->mass_factor != 1) return "mass_factor must be 0 or 1";
-    if (!(c->r_cam > 0.0) || !(c->r_cam > 2.0 * horizon(c->a, c->mass_factor)))
-        return "r_cam must exceed twice the horizon radius";
-    if (c->nx < 1 || c->ny < 1) return "nx and ny must be >= 1";
-    if ((int64_t)c->nx * c->ny > (int64_t)INT32_MAX / 2) return "image too large";
-    if (!(c->freq_hz > 0.0)) return "freq_hz must be > 0";
-    if (!(c->eps > 0.0 && c->eps <= 0.5)) return "eps must satisfy 0 < eps <= 0.5";
-    if (c->max_steps < 1) return "max_steps must be >= 1";
-    if (!(c->incl_deg > 0.0 && c->incl_deg < 180.0)) return "incl_deg must be in (0, 180)";
-    if (!(c->fov_x > 0.0 && c->fov_y > 0.0)) return "field of view must be > 0";
-    if (c->jitter != 0 && c->jitter != 1) return "jitter must be 0 or 1";
-    return "";
-}
+using krt_host::check_camera;
+using krt_host::finite_all;
+using krt_host::horizon;
+using krt_host::isco;
 
 CameraDesc camera_desc(const krt_camera* c) {
     CameraDesc d;
@@ -755,9 +725,8 @@ krt_status krt_set_stream(krt_ctx* ctx, void* hip_stream) {
 
 krt_status krt_set_units(krt_ctx* ctx, const krt_units* u) {
     if (!ctx) return KRT_E_INVAL;
-    if (!u || u->struct_size != sizeof(krt_units)) return fail(ctx, KRT_E_INVAL, "bad units struct");
-    if (!(std::isfinite(u->M_bh_g) && u->M_bh_g > 0.0 && std::isfinite(u->dist_cm) && u->dist_cm > 0.0))
-        return fail(ctx, KRT_E_INVAL, "units must be finite and > 0");
+    const std::string m = krt_host::check_units(u);
+    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
     ctx->units = *u;
     ctx->units_set = true;
     return KRT_OK;
@@ -765,11 +734,9 @@ krt_status krt_set_units(krt_ctx* ctx, const krt_units* u) {
 
 krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* p) {
     if (!ctx) return KRT_E_INVAL;
-    if (!p || p->struct_size != sizeof(krt_adaf)) return fail(ctx, KRT_E_INVAL, "bad adaf struct");
-    if (!finite_all({p->n0_cgs, p->T0_K, p->beta, p->h_over_r}) || !(p->n0_cgs >= 0.0) ||
-        !(p->T0_K > 0.0) || !(p->beta > 0.0) || !(p->h_over_r > 0.0))
-        return fail(ctx, KRT_E_INVAL, "ADAF parameters must be finite, n0 >= 0, T0, beta, h > 0");
-    if (p->field_geom != 0) return fail(ctx, KRT_E_UNSUPPORTED, "only toroidal fields (0) are supported");
+    bool unsup = false;
+    const std::string m = krt_host::check_adaf(p, &unsup);
+    if (!m.empty()) return fail(ctx, unsup ? KRT_E_UNSUPPORTED : KRT_E_INVAL, m);
     ctx->adaf = *p;
     ctx->model = kModelAdaf;
     return KRT_OK;
@@ -778,21 +745,10 @@ krt_status krt_set_model_adaf(krt_ctx* ctx, const krt_adaf* p) {
 krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, const void* d_prims,
                                   int dtype) {
     if (!ctx) return KRT_E_INVAL;
-    if (!desc || desc->struct_size != sizeof(krt_snapshot_desc)) return fail(ctx, KRT_E_INVAL, "bad snapshot struct");
-    if (!d_prims) return fail(ctx, KRT_E_INVAL, "d_prims is NULL");
-    if (dtype != KRT_DTYPE_F64 && dtype != KRT_DTYPE_F32)
-        return fail(ctx, KRT_E_UNSUPPORTED, "dtype must be KRT_DTYPE_F64 or KRT_DTYPE_F32");
-    if (desc->layout != 0 && desc->layout != 1)
-        return fail(ctx, KRT_E_UNSUPPORTED, "layout must be 0 ([n1][n2][n3][8]) or 1 ([8][n1][n2][n3])");
+    bool unsup = false;
+    const std::string m = krt_host::check_snapshot(desc, d_prims, dtype, &unsup);
+    if (!m.empty()) return fail(ctx, unsup ? KRT_E_UNSUPPORTED : KRT_E_INVAL, m);
     const krt_snapshot_desc& d = *desc;
-    if (d.n1 < 2 || d.n2 < 2 || d.n3 < 1) return fail(ctx, KRT_E_INVAL, "grid needs n1, n2 >= 2 and n3 >= 1");
-    if ((int64_t)d.n1 * d.n2 * d.n3 > ((int64_t)1 << 31) / 8) return fail(ctx, KRT_E_INVAL, "grid too large");
-    if (!finite_all({d.x1_start, d.dx1, d.x2_start, d.dx2, d.x3_start, d.dx3, d.hslope, d.gamma_ad, d.M_unit_g,
-                     d.R_high, d.R_low, d.sigma_cut, d.r_emit_max}))
-        return fail(ctx, KRT_E_INVAL, "snapshot description has a non-finite field");
-    if (!(d.dx1 > 0.0 && d.dx2 > 0.0 && d.dx3 > 0.0)) return fail(ctx, KRT_E_INVAL, "cell sizes must be > 0");
-    if (!(d.M_unit_g > 0.0) || !(d.gamma_ad > 1.0)) return fail(ctx, KRT_E_INVAL, "need M_unit > 0, gamma_ad > 1");
-    if (!(d.hslope > 0.0 && d.hslope <= 1.0)) return fail(ctx, KRT_E_INVAL, "hslope must be in (0, 1]");
     if (d.layout == 1) {
         // one transpose into the library's copy in the gather's layout (the
         // copy is read instead of d_prims from now on)
@@ -907,14 +863,8 @@ krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint
 
 krt_status krt_set_launch_config(krt_ctx* ctx, const krt_launch_config* cfg) {
     if (!ctx) return KRT_E_INVAL;
-    if (!cfg || cfg->struct_size != sizeof(krt_launch_config)) return fail(ctx, KRT_E_INVAL, "bad config struct");
-    const int tw = cfg->tile_w;
-    if (!(tw == 4 || tw == 8 || tw == 16 || tw == 32 || tw == 64))
-        return fail(ctx, KRT_E_INVAL, "tile_w must be 4, 8, 16, 32 or 64");
-    if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 16) return fail(ctx, KRT_E_INVAL, "blocks_per_cu must be 0..16");
-    if (cfg->path_cap != 0 && (cfg->path_cap < 64 || cfg->path_cap > 65536))
-        return fail(ctx, KRT_E_INVAL, "path_cap must be 0 or 64..65536");
-    if (cfg->order < 0 || cfg->order > 2) return fail(ctx, KRT_E_INVAL, "order must be 0, 1 or 2");
+    const std::string m = krt_host::check_launch_config(cfg);
+    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
     ctx->cfg = *cfg;
     return KRT_OK;
 }
