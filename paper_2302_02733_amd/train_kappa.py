@@ -87,7 +87,12 @@ def main():
         meta = {"epochs": args.epochs, "rounds": args.rounds, "batch": args.batch, "lr_max": args.lr,
                 "train_samples": int(tr_in.shape[0]), "train_seed": 13, "test_samples": int(te_in.shape[0]),
                 "test_seed": 17, "init_seed": args.init_seed, "final_loss": loss, "train_seconds": t_train,
-                "set_seconds": t_set, "test_rel_err": err, "integrals": NAMES}
+                "set_seconds": t_set, "test_rel_err": err, "integrals": NAMES,
+                "train_targets": ("exact integrals from the library's own integrator (krt_kappa_integrals: "
+                                  "Chebyshev table of the synchrotron functions, 361-node trapezoid rule in "
+                                  "ln(g-1)), which agrees with the CPU oracle's integrator to 5e-10 "
+                                  "(tests/test_gpu_kappa.py); the oracle itself is test infrastructure and "
+                                  "takes no part in training")}
         np.savez(args.out, params=params, norm=norm, meta=np.array(json.dumps(meta)))
         print(json.dumps(meta))
     return 0
