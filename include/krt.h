@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 5
+#define KRT_ABI_VERSION 6
 
 typedef enum {
     KRT_OK = 0,
@@ -227,6 +227,22 @@ krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint
  * d_nsteps ([ny][nx] int32, may be NULL).  Same errors as krt_trace. */
 krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes,
                            uint8_t* d_status, int32_t* d_nsteps, krt_stats* out_stats);
+
+/* Measurement probe of the per-ray work of the image traced by krt_trace
+ * (Sec. 2.2 reports the GPU's throughput; this hook lets hardware instruction
+ * counters see that work without lane divergence): each listed pixel
+ * (pixels: HOST array of npix row-major indices into the camera's nx x ny
+ * image, copied by the call) is traced by all 64 lanes of one wavefront, with
+ * the same per-ray arithmetic as krt_trace.  d_stokes: [4][npix] FP64, the
+ * listed pixels' Stokes vectors (equal to krt_trace's values of those pixels).
+ * out_stats (may be NULL) counts every lane: rays = 64 npix and total_steps =
+ * 64 x the listed rays' steps.  Thermal electrons only.  Synchronous.
+ * Errors: KRT_E_INVAL (empty list, index outside the image, bad camera),
+ * KRT_E_STATE, KRT_E_UNSUPPORTED (kappa electrons), KRT_E_NOMEM (also when a
+ * listed ray outgrows the path store: the probe has no long-ray pass),
+ * KRT_E_HIP. */
+krt_status krt_trace_probe(krt_ctx* ctx, const krt_camera* cam, const int32_t* pixels, int32_t npix,
+                           double* d_stokes, krt_stats* out_stats);
 
 /* ---- batched image libraries ---- */
 

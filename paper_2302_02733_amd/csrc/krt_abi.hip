@@ -52,6 +52,9 @@ struct krt_ctx {
     int32_t* overflow_list = nullptr;
     int32_t* overflow_inst = nullptr;
     size_t overflow_cap = 0;
+    // pixel list of the measurement probe
+    int32_t* probe_dev = nullptr;
+    size_t probe_cap = 0;
     // launch configuration (tile shape, grid, slice size)
     krt_launch_config cfg{sizeof(krt_launch_config), 8, 0, 0, 1};
     // batch descriptors: device copy and pinned staging
@@ -704,6 +707,7 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->btab) (void)hipFree(ctx->btab);
     if (ctx->syntab) (void)hipFree(ctx->syntab);
     if (ctx->tile_order) (void)hipFree(ctx->tile_order);
+    if (ctx->probe_dev) (void)hipFree(ctx->probe_dev);
     if (ctx->snap_copy) (void)hipFree(ctx->snap_copy);
     if (ctx->mlp_P) (void)hipFree(ctx->mlp_P);
     if (ctx->mlp_m) (void)hipFree(ctx->mlp_m);
@@ -793,13 +797,26 @@ krt_status krt_set_precision(krt_ctx* ctx, int precision) {
     return KRT_OK;
 }
 
-krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
-                           int32_t* d_nsteps, krt_stats* out_stats) {
+}  // extern "C"
+
+namespace {
+
+// The plain tracer over the whole image, or (probe_np > 0) over the listed
+// pixels, each traced by all 64 lanes of a wave (probe_host: host array).
+krt_status trace_plain(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
+                       int32_t* d_nsteps, krt_stats* out_stats, const int32_t* probe_host, int32_t probe_np) {
     krt_status st = check_ready(ctx, cam);
     if (st != KRT_OK) return st;
     if (!d_stokes) return fail(ctx, KRT_E_INVAL, "d_stokes is NULL");
+    if (probe_np > 0) {
+        const int64_t np = (int64_t)cam->nx * cam->ny;
+        for (int32_t k = 0; k < probe_np; ++k)
+            if (probe_host[k] < 0 || probe_host[k] >= np) return fail(ctx, KRT_E_INVAL, "probe pixel out of the image");
+        if (ctx->electrons != KRT_ELECTRONS_THERMAL)
+            return fail(ctx, KRT_E_UNSUPPORTED, "the probe traces thermal electrons only");
+    }
     KRT_HIP(ctx, hipSetDevice(ctx->device));
-    const size_t npix = (size_t)cam->nx * cam->ny;
+    const size_t npix = probe_np > 0 ? (size_t)probe_np * 64 : (size_t)cam->nx * cam->ny;
     const int el = ctx->electrons;
     const bool f32 = el == KRT_ELECTRONS_THERMAL && ctx->precision == KRT_PRECISION_FP32_TRANSFER;
     if (el == KRT_ELECTRONS_KAPPA_SURROGATE && !ctx->mlp_ready)
@@ -830,6 +847,30 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     A.stokes = d_stokes;
     A.status = d_status;
     A.nsteps = d_nsteps;
+    if (probe_np > 0) {
+        if (ctx->probe_cap < (size_t)probe_np) {
+            KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->probe_dev) KRT_HIP(ctx, hipFree(ctx->probe_dev));
+            ctx->probe_dev = nullptr;
+            ctx->probe_cap = 0;
+            if (hipMalloc(&ctx->probe_dev, (size_t)probe_np * sizeof(int32_t)) != hipSuccess) {
+                ctx->probe_dev = nullptr;
+                (void)hipGetLastError();
+                return fail(ctx, KRT_E_NOMEM, "cannot allocate the probe list");
+            }
+            ctx->probe_cap = (size_t)probe_np;
+        }
+        KRT_HIP(ctx, hipMemcpyAsync(ctx->probe_dev, probe_host, (size_t)probe_np * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, ctx->stream));
+        KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        A.probe_pix = ctx->probe_dev;
+        A.probe_np = probe_np;
+        A.nbatch = probe_np;
+        A.tile_order = nullptr;
+        A.nsec = 1;
+        A.status = nullptr;
+        A.nsteps = nullptr;
+    }
     KRT_HIP(ctx, hipMemsetAsync(ctx->work, 0, kWorkWords * sizeof(unsigned), ctx->stream));
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[0], ctx->stream));
     const dim3 grid(ctx->launch_blocks), lgrid(ctx->long_slots / 64);
@@ -843,6 +884,15 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
         hipLaunchKernelGGL(trace_waves<kModeF64>, grid, dim3(256), 0, ctx->stream, A);
     KRT_HIP(ctx, hipGetLastError());
     if (out_stats) KRT_HIP(ctx, hipEventRecord(ctx->ev[1], ctx->stream));
+    if (probe_np > 0) {
+        // no long-ray pass: a probe ray that outgrew the store is an error
+        krt_stats s{};
+        krt_stats* sp = out_stats ? out_stats : &s;
+        KRT_HIP(ctx, hipEventRecord(ctx->ev[2], ctx->stream));
+        if ((st = fill_stats(ctx, (int64_t)npix, sp)) != KRT_OK) return st;
+        if (sp->long_rays > 0) return fail(ctx, KRT_E_NOMEM, "a probe ray outgrew the path store");
+        return KRT_OK;
+    }
     // long rays of either kappa mode use the exact integrator
     if (el != KRT_ELECTRONS_THERMAL)
         hipLaunchKernelGGL(trace_long<kModeKapExact>, lgrid, dim3(64), 0, ctx->stream, A);
@@ -856,9 +906,25 @@ krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes
     return KRT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+krt_status krt_trace_steps(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
+                           int32_t* d_nsteps, krt_stats* out_stats) {
+    return trace_plain(ctx, cam, d_stokes, d_status, d_nsteps, out_stats, nullptr, 0);
+}
+
 krt_status krt_trace(krt_ctx* ctx, const krt_camera* cam, double* d_stokes, uint8_t* d_status,
                      krt_stats* out_stats) {
-    return krt_trace_steps(ctx, cam, d_stokes, d_status, nullptr, out_stats);
+    return trace_plain(ctx, cam, d_stokes, d_status, nullptr, out_stats, nullptr, 0);
+}
+
+krt_status krt_trace_probe(krt_ctx* ctx, const krt_camera* cam, const int32_t* pixels, int32_t npix,
+                           double* d_stokes, krt_stats* out_stats) {
+    if (!ctx) return KRT_E_INVAL;
+    if (!pixels || npix < 1) return fail(ctx, KRT_E_INVAL, "empty probe pixel list");
+    return trace_plain(ctx, cam, d_stokes, nullptr, nullptr, out_stats, pixels, npix);
 }
 
 krt_status krt_set_launch_config(krt_ctx* ctx, const krt_launch_config* cfg) {

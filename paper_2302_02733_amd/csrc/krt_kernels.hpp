@@ -83,6 +83,10 @@ struct TraceArgs {
     double kappa;
     const double* syntab;       // synchrotron-function table
     const MlpPacked* mlp;       // packed surrogate
+    // measurement probe (plain mode): queue item t is listed pixel probe_pix[t],
+    // traced by all 64 lanes of the wave; Stokes written as [4][probe_np]
+    const int32_t* probe_pix;
+    int probe_np;
 };
 
 // ---------------------------------------------------------------------------
@@ -217,64 +221,58 @@ KRT_HD void load_point(const double* p, double v[8]) {
 }
 
 // ---------------------------------------------------------------------------
-// Uniform FP64 parameters (spin, mass, camera, plasma model) are kernel
-// arguments in scalar registers, but FP64 arithmetic runs only on the vector
-// ALU, so every loop-invariant expression of them that the optimizer hoists out
-// of the persistent loops holds a vector register pair for the whole kernel.
-// Passing them through an empty asm inside the loop that uses them makes them
-// opaque there: the few derived values are recomputed where they are needed
-// and the registers go to the per-ray state instead.
+// Uniform parameters (spin, mass, camera, plasma model, buffers) are read
+// where they are used.  Kept for the whole persistent kernel they would fill
+// the scalar register file, spill into vector-register lanes and cost one
+// VALU lane read per word at every use (about 300 per ray-step); a loop-
+// invariant FP64 expression of them hoisted out of the loops would hold a
+// vector register pair.  Instead the hot loops re-read them with scalar loads
+// (scalar cache, no VALU issue) through a pointer that an empty asm makes
+// opaque at each use, so neither the loads nor what is computed from them can
+// be hoisted.  The source is the kernel-argument segment (the plain tracer),
+// or the argument segment overlaid with a geodesic group's and an image
+// instance's descriptors (the batched library); descriptors live in device
+// memory that no kernel writes while a trace runs, so they may be read through
+// the constant address space.
 // ---------------------------------------------------------------------------
-KRT_HD double opaque(double x) {
+template <class T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
+template <class T>
+__device__ __forceinline__ T fresh_copy(const T* p) {
+    ConstPtr<T> q = (ConstPtr<T>)p;
 #if defined(__HIP_DEVICE_COMPILE__)
-    asm volatile("" : "+s"(x));
+    asm volatile("" : "+s"(q));
 #endif
-    return x;
+    T v;
+    __builtin_memcpy(&v, (const T*)q, sizeof(T));
+    return v;
 }
 
-KRT_HD void launder_camera(CameraDesc& c) {
-    c.a = opaque(c.a);
-    c.m = opaque(c.m);
-    c.r_cam = opaque(c.r_cam);
-    c.th = opaque(c.th);
-    c.ph = opaque(c.ph);
-    c.fov_x = opaque(c.fov_x);
-    c.fov_y = opaque(c.fov_y);
-    c.freq = opaque(c.freq);
+// The tables a block stages in LDS (their addresses are fixed at compile time).
+struct LdsTables {
+    const double* btab;
+    const float* btab_f;
+    const MlpPacked* mlp;
+};
+
+KRT_HD void use_lds(TraceArgs& L, const LdsTables& T) {
+    if (T.btab) L.btab = T.btab;
+    if (T.btab_f) L.btab_f = T.btab_f;
+    if (T.mlp) L.mlp = T.mlp;
 }
 
-// The parameters read by the transfer at one point.
-KRT_HD void launder_transfer(TraceArgs& L) {
-    L.cam.a = opaque(L.cam.a);
-    L.cam.m = opaque(L.cam.m);
-    L.cam.freq = opaque(L.cam.freq);
-    L.fac0 = opaque(L.fac0);
-    if (L.model == kModelSnapshot) {
-        SnapDesc& q = L.snap;
-        q.x1s = opaque(q.x1s);
-        q.dx1 = opaque(q.dx1);
-        q.x2s = opaque(q.x2s);
-        q.dx2 = opaque(q.dx2);
-        q.x3s = opaque(q.x3s);
-        q.dx3 = opaque(q.dx3);
-        q.h = opaque(q.h);
-        q.gam = opaque(q.gam);
-        q.rho_unit = opaque(q.rho_unit);
-        q.B_unit = opaque(q.B_unit);
-        q.Rhigh = opaque(q.Rhigh);
-        q.Rlow = opaque(q.Rlow);
-        q.sigma_cut = opaque(q.sigma_cut);
-        q.rmax = opaque(q.rmax);
-    } else {
-        L.adaf.n0 = opaque(L.adaf.n0);
-        L.adaf.T0 = opaque(L.adaf.T0);
-        L.adaf.beta = opaque(L.adaf.beta);
-        L.adaf.h = opaque(L.adaf.h);
-        L.adaf.ibeta = opaque(L.adaf.ibeta);
-        L.adaf.i2h2 = opaque(L.adaf.i2h2);
-        L.adaf.risco = opaque(L.adaf.risco);
+// Parameters of the plain tracer: its arguments (args: the kernel-argument
+// segment, which holds them at offset 0) with the block's LDS tables.
+struct PlainSource {
+    const TraceArgs* args;
+    LdsTables lds;
+    __device__ __forceinline__ TraceArgs operator()() const {
+        TraceArgs L = fresh_copy(args);
+        use_lds(L, lds);
+        return L;
     }
-}
+};
 
 // ---------------------------------------------------------------------------
 // Transfer state between stored points (Heun transport split in two halves):
@@ -619,6 +617,11 @@ __device__ __forceinline__ uint8_t write_pixel(const TraceArgs& A, int pix, doub
         S[0] = S[1] = S[2] = S[3] = 0.0;
         st = kNonFinite;
     }
+    if (A.probe_pix) {   // the 64 copies are equal: lane 0 writes
+        if ((threadIdx.x & 63) == 0)
+            for (int k = 0; k < 4; ++k) A.stokes[(size_t)k * A.probe_np + pix] = S[k];
+        return st;
+    }
     const size_t np = (size_t)A.cam.nx * A.cam.ny;
     for (int k = 0; k < 4; ++k) A.stokes[k * np + pix] = S[k];
     if (A.status) A.status[pix] = st;
@@ -697,11 +700,13 @@ __device__ __forceinline__ void kappa_account(const TraceArgs& A, unsigned n_mlp
 // Transfer phase of one tile (all lanes on the same point index, far end
 // first), output and accounting.  Rays that overflowed the store are queued
 // for the long-ray kernel (with their instance in batch mode).
-template <int kMode>
-__device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot, const int* wchunks,
+// src() gives the parameters (read where they are used).
+template <int kMode, class Src>
+__device__ __forceinline__ void trace_transfer(const Src& src, double* slot, const int* wchunks,
                                                int lane, bool valid, int pix, double alpha, double beta,
                                                uint8_t st, int n) {
     if (valid && st == kOverflow) {
+        const TraceArgs A = src();
         const unsigned k = atomicAdd(A.overflow_count, 1u);
         A.overflow_list[k] = pix;
         if (A.overflow_inst) A.overflow_inst[k] = A.inst_id;
@@ -728,8 +733,9 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
     // waves per SIMD covering the load, it gains nothing.
     constexpr bool kPrefetch = kMode == kModeKapExact;
     double nxt[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr(A, slot, wchunks, nmax, lane), nxt);
+    if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr(src(), slot, wchunks, nmax, lane), nxt);
     for (int m = nmax; m >= 0; --m) {
+        const TraceArgs A = src();
         if constexpr (kMode == kModeKapMlp) {
             // surrogate inputs of this lane's point (in-domain points only),
             // the network for the whole wave, then the update
@@ -785,23 +791,20 @@ __device__ __forceinline__ void trace_transfer(const TraceArgs& A, double* slot,
                 if (m > n_end) continue;
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
             }
-            TraceArgs L = A;
-            launder_transfer(L);
             if constexpr (kMode == kModeF32)
-                transfer_point_f32(L, pt, m, m == n_end, xs, N);
+                transfer_point_f32(A, pt, m, m == n_end, xs, N);
             else if constexpr (kMode == kModeKapExact)
                 transfer_point_kappa(A, pt, m, m == n_end, xs, N, nullptr, false, n_exact);
             else
-                transfer_point(L, pt, m, m == n_end, xs, N);
+                transfer_point(A, pt, m, m == n_end, xs, N);
         }
     }
+    const TraceArgs A = src();
     if constexpr (kKappa<kMode>) kappa_account(A, n_mlp, n_exact);
     uint8_t st_out = st;
     if (xfer) {
         double S[4];
-        TraceArgs L = A;
-        launder_camera(L.cam);
-        camera_output(L, alpha, beta, N, S);
+        camera_output(A, alpha, beta, N, S);
         st_out = write_pixel(A, pix, S, st, n);
     }
     // counted with the status written (a non-finite Stokes vector turns the
@@ -821,16 +824,15 @@ __device__ __forceinline__ void tile_pixel(int tiles_x, int tile_w, int tile, in
 // Geodesic phase of one tile: camera launch and RK4 steps in lockstep, every
 // point stored in the wave's slice, then in chunks of the paged store (kStore),
 // or only the end state kept.  Returns the number of chunks the wave holds.
-template <bool kStore>
-__device__ __forceinline__ int geodesic_phase(const TraceArgs& A, bool valid, int i, int j, double* slot,
+template <bool kStore, class Src>
+__device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i, int j, double* slot,
                                               int* wchunks, size_t wave, int lane, double& alpha,
                                               double& beta, double y[7], double& hlast, uint8_t& st,
                                               int& n) {
     alpha = 0.0;
     beta = 0.0;
     {
-        CameraDesc C = A.cam;
-        launder_camera(C);
+        const CameraDesc C = src().cam;
         pixel_position(C, valid ? i : 0, valid ? j : 0, alpha, beta);
         double X[4], K[4];
         camera_launch(C, alpha, beta, X, K);
@@ -850,7 +852,8 @@ __device__ __forceinline__ int geodesic_phase(const TraceArgs& A, bool valid, in
     int nch = 0, cstart = 0;
     double* cbase = slot;
     while (st == kRunning) {
-        const double h = rk4_step(opaque(A.cam.a), opaque(A.cam.m), opaque(A.eps), y, sn, cs);
+        const TraceArgs A = src();
+        const double h = rk4_step(A.cam.a, A.cam.m, A.eps, y, sn, cs);
         ++n;
         hlast = h;
         if (kStore) {
@@ -917,22 +920,26 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2
         __syncthreads();
         A.mlp = reinterpret_cast<const MlpPacked*>(s_mlp);
     }
+    const PlainSource src{(const TraceArgs*)__builtin_amdgcn_kernarg_segment_ptr(),
+                          {kMode == kModeF64 ? s_btab : nullptr, kMode == kModeF32 ? s_btab_f : nullptr,
+                           kMode == kModeKapMlp ? reinterpret_cast<const MlpPacked*>(s_mlp) : nullptr}};
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: read it from the first lane so that the
     // slice address lives in scalar registers
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) +
                         (size_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
     __shared__ int s_chunks[4][kMaxChunks];
     int* wchunks = s_chunks[threadIdx.x >> 6];
     // With sectors, blocks are dealt to the XCDs in turn (block b on XCD
     // b mod 8), so a wave starts on the sector of its XCD, whose tiles lie
     // together on the image (and their snapshot cells in that XCD's L2), and
     // moves on to the next sectors when its own is drained.
-    const int nsec = A.nsec;
-    int sec = nsec > 1 ? (int)(blockIdx.x % (unsigned)nsec) : 0;
+    int sec = A.nsec > 1 ? (int)(blockIdx.x % (unsigned)A.nsec) : 0;
     int drained = 0;
     for (;;) {
+        const TraceArgs A = src();
+        const int nsec = A.nsec;
+        double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
         // One queue ticket per wave, taken without a lane-divergent branch:
         // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
         // as a scalar, so the loop exit below is wave-uniform.
@@ -954,14 +961,20 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2
         }
         int i, j;
         tile_pixel(A.tiles_x, A.tile_w, tile, lane, i, j);
+        if (A.probe_pix) {
+            const int p = A.probe_pix[tile];
+            i = p % A.cam.nx;
+            j = p / A.cam.nx;
+        }
         const bool valid = i < A.cam.nx && j < A.cam.ny;
-        const int pix = j * A.cam.nx + i;
+        const int pix = A.probe_pix ? tile : j * A.cam.nx + i;
         double alpha, beta, hlast, y[7];
         uint8_t st;
         int n;
         const int nch_w =
-            geodesic_phase<!kGeoOnly>(A, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y, hlast, st, n);
+            geodesic_phase<!kGeoOnly>(src, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y, hlast, st, n);
         if (kGeoOnly) {
+            const TraceArgs A = src();
             if (valid) {
                 double* e = A.end_state + (size_t)pix * 8;
                 for (int k = 0; k < 7; ++k) e[k] = y[k];
@@ -972,8 +985,7 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2
                     // constants of the motion at the camera (the launch state,
                     // recomputed) and at the last point
                     double y0[7], c0[4], c1[4];
-                    CameraDesc C = A.cam;
-                    launder_camera(C);
+                    const CameraDesc C = A.cam;
                     double X[4], K[4];
                     camera_launch(C, alpha, beta, X, K);
                     y0[0] = X[1]; y0[1] = X[2]; y0[2] = X[3];
@@ -986,7 +998,8 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2
             }
             account(A, valid, st, n);
         } else {
-            trace_transfer<kMode>(A, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
+            trace_transfer<kMode>(src, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
+            const TraceArgs A = src();
             if (lane == 0)
                 for (int k = 0; k < nch_w; ++k) atomicExch(&A.chunk_flags[wchunks[k]], 0u);
         }
@@ -1018,21 +1031,6 @@ struct InstDev {
     int group;
 };
 
-// Copy of a descriptor that all lanes of the wave load from the same address,
-// moved into scalar registers word by word (the kernel writes global memory,
-// so the compiler cannot prove the descriptor invariant and loads it into
-// vector registers).
-template <class T>
-__device__ __forceinline__ T wave_uniform(const T& v) {
-    static_assert(sizeof(T) % 4 == 0, "descriptor size");
-    T out;
-    const int* src = reinterpret_cast<const int*>(&v);
-    int* dst = reinterpret_cast<int*>(&out);
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
-    return out;
-}
-
 KRT_HD void apply_group(TraceArgs& L, const GroupDev& G) {
     L.cam = G.cam;
     L.eps = G.eps;
@@ -1054,29 +1052,44 @@ KRT_HD void apply_instance(TraceArgs& L, const InstDev& I, int q) {
     L.inst_id = q;
 }
 
+// Parameters of a batch item: the kernel arguments overlaid with geodesic
+// group g and (q >= 0) image instance q, read where they are used.
+struct BatchSource {
+    PlainSource base;
+    int g, q;
+    __device__ __forceinline__ TraceArgs operator()() const {
+        TraceArgs L = base();
+        apply_group(L, fresh_copy(L.groups + g));
+        if (q >= 0) apply_instance(L, fresh_copy(L.inst + q), q);
+        return L;
+    }
+};
+
 template <int kMode>
 __global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
     constexpr int kTab = kBesPanels * 2 * kBesCoef;
     __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
     __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
     stage_table<kMode>(A, s_btab, s_btab_f);
+    const PlainSource base{(const TraceArgs*)__builtin_amdgcn_kernarg_segment_ptr(),
+                           {kMode == kModeF64 ? s_btab : nullptr, kMode == kModeF32 ? s_btab_f : nullptr,
+                            nullptr}};
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: read it from the first lane so that the
     // slice address lives in scalar registers
     const size_t wave = (size_t)blockIdx.x * (blockDim.x >> 6) +
                         (size_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
     __shared__ int s_chunks[4][kMaxChunks];
     int* wchunks = s_chunks[threadIdx.x >> 6];
     for (;;) {
+        const TraceArgs A = base();
+        double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
         const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
         const int item = __builtin_amdgcn_readfirstlane((int)ticket);
         if (item >= A.nbatch) break;
         int g = 0;
-        while (g < A.ngroups - 1 && item >= __builtin_amdgcn_readfirstlane(A.groups[g].item_end)) ++g;
-        const GroupDev G = wave_uniform(A.groups[g]);
-        TraceArgs Ag = A;
-        apply_group(Ag, G);
+        while (g < A.ngroups - 1 && item >= fresh_copy(A.groups + g).item_end) ++g;
+        const GroupDev G = fresh_copy(A.groups + g);
         int i, j;
         tile_pixel(G.tiles_x, A.tile_w, item - G.item_begin, lane, i, j);
         const bool valid = i < G.cam.nx && j < G.cam.ny;
@@ -1084,15 +1097,12 @@ __global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
         double alpha, beta, hlast, y[7];
         uint8_t st;
         int n;
-        const int nch_w =
-            geodesic_phase<true>(Ag, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y, hlast, st, n);
-        for (int q = G.inst_begin; q < G.inst_end; ++q) {
-            TraceArgs Ai = Ag;
-            apply_instance(Ai, wave_uniform(A.inst[q]), q);
-            trace_transfer<kMode>(Ai, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
-        }
+        const int nch_w = geodesic_phase<true>(BatchSource{base, g, -1}, valid, i, j, slot, wchunks, wave, lane,
+                                               alpha, beta, y, hlast, st, n);
+        for (int q = G.inst_begin; q < G.inst_end; ++q)
+            trace_transfer<kMode>(BatchSource{base, g, q}, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
         if (lane == 0)
-            for (int k = 0; k < nch_w; ++k) atomicExch(&A.chunk_flags[wchunks[k]], 0u);
+            for (int k = 0; k < nch_w; ++k) atomicExch(&base().chunk_flags[wchunks[k]], 0u);
     }
 }
 
@@ -1124,7 +1134,7 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         const int i = pix % R.cam.nx, j = pix / R.cam.nx;
         double alpha, beta, y[7];
         // the parameters can differ from lane to lane here (batch instances),
-        // so they stay in vector registers and are not laundered
+        // so they stay in vector registers (read once per ray)
         const CameraDesc C = R.cam;
         pixel_position(C, i, j, alpha, beta);
         {

@@ -104,6 +104,8 @@ _SIGS = {
     "krt_set_model_snapshot": (ctypes.c_int, [_P, ctypes.POINTER(SnapshotDesc), _P, ctypes.c_int]),
     "krt_trace": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, ctypes.POINTER(Stats)]),
     "krt_trace_steps": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P, ctypes.POINTER(Stats)]),
+    "krt_trace_probe": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, ctypes.c_int32, _P,
+                                       ctypes.POINTER(Stats)]),
     "krt_reduce": (ctypes.c_int, [_P, _P, ctypes.POINTER(Camera), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]),
     "krt_last_error": (ctypes.c_char_p, [_P]),
@@ -334,6 +336,26 @@ class Context:
                                           _ptr(nsteps), ctypes.byref(st) if stats else None))
         return {"stokes": stokes, "status": status, "nsteps": nsteps,
                 "stats": st.as_dict() if stats else None}
+
+    def trace_probe(self, cam, pixels, stokes=None):
+        """Measurement probe: every listed row-major pixel of the camera's image
+        traced by the 64 lanes of one wave (no lane divergence).  Returns
+        dict(stokes [4, npix] f64, stats dict)."""
+        import numpy as np
+        pix = np.ascontiguousarray(pixels, dtype=np.int32)
+        n = int(pix.shape[0])
+        if stokes is None:
+            stokes = torch.empty((4, n), dtype=torch.float64, device=self.device)
+        _dev(stokes, self.device)
+        if tuple(stokes.shape) != (4, n) or stokes.dtype != torch.float64:
+            raise ValueError("bad output tensor")
+        c = make_camera(cam)
+        st = Stats()
+        st.struct_size = ctypes.sizeof(Stats)
+        self._stream()
+        self._check(lib().krt_trace_probe(self.h, ctypes.byref(c), pix.ctypes.data_as(_P), n, _ptr(stokes),
+                                          ctypes.byref(st)))
+        return {"stokes": stokes, "stats": st.as_dict()}
 
     def reduce(self, stokes, cam):
         """Returns (flux_jy[4], I_max); synchronises."""

@@ -200,3 +200,43 @@ def test_field_major_snapshot_layout_gives_the_same_image(krt, snap48, f32):
         So, sto, nso = oracle.render(cam, w["units"], w["model"], snap=h)
         Sb = b.cpu().numpy()
         assert abs(Sb[0].sum() - So[0].sum()) <= 1e-10 * So[0].sum()
+
+
+@pytest.mark.parametrize("model", ["adaf", "snapshot"])
+@pytest.mark.parametrize("f32", [False, True])
+def test_probe_equals_the_image(krt, snap48, model, f32):
+    """The measurement probe traces each listed pixel with all 64 lanes of a
+    wave: its Stokes vectors equal the image's bit for bit, and its counters
+    hold 64 x the listed rays' steps."""
+    if model == "adaf":
+        cam, units = W.adaf_camera(64), W.UNITS
+    else:
+        w, desc, P = snap48
+        cam, units = w["camera"], w["units"]
+    rng = np.random.default_rng(5)
+    pix = rng.choice(cam["nx"] * cam["ny"], size=97, replace=False).astype(np.int32)
+    with krt.Context(0) as ctx:
+        ctx.set_units(units)
+        if f32:
+            ctx.set_precision(krt.PRECISION_FP32_TRANSFER)
+        if model == "adaf":
+            ctx.set_model(W.ADAF)
+        else:
+            t = torch.tensor(P, device="cuda", dtype=torch.float32 if f32 else torch.float64)
+            ctx.set_model_snapshot(desc, t)
+        ns = torch.empty((cam["ny"], cam["nx"]), dtype=torch.int32, device="cuda")
+        _log(f"probe {model} f32={f32}: image")
+        img = ctx.trace(cam, nsteps=ns)
+        _log(f"probe {model} f32={f32}: {len(pix)} pixels")
+        pr = ctx.trace_probe(cam, pix)
+        S = img["stokes"].reshape(4, -1).cpu().numpy()[:, pix]
+        Sp = pr["stokes"].cpu().numpy()
+        nsp = ns.reshape(-1).cpu().numpy()[pix]
+        stats = pr["stats"]
+        # an index outside the image is rejected on the host
+        with pytest.raises(krt.KrtError) as e:
+            ctx.trace_probe(cam, np.array([cam["nx"] * cam["ny"]], dtype=np.int32))
+        assert e.value.code == krt.E_INVAL
+    assert np.array_equal(S, Sp)
+    assert stats["rays"] == 64 * len(pix)
+    assert stats["total_steps"] == 64 * int(nsp.sum())

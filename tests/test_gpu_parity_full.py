@@ -27,11 +27,33 @@ from paper_2302_02733_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SAMPLE = 1 << 16
+CHUNK_ROWS = 32
+
+
+_emit = None
+
+
+@pytest.fixture(autouse=True)
+def _progress(capsys):
+    """Progress lines go straight to the terminal (not captured), so that a
+    long oracle run shows that it is alive."""
+    global _emit
+
+    def emit(msg):
+        with capsys.disabled():
+            print(msg, flush=True)
+    _emit = emit
+    yield
+    _emit = None
 
 
 def _log(msg):
     import sys
-    print(f"[gpu-test] {msg}", file=sys.stderr, flush=True)
+    line = f"[gpu-test] {msg}"
+    if _emit is not None:
+        _emit(line)
+    else:
+        print(line, file=sys.stderr, flush=True)
 
 
 @pytest.fixture(scope="module")
@@ -56,8 +78,22 @@ def _oracle(w, pix, snap=None):
     t0 = time.perf_counter()
     _log(f"oracle {cam['nx']}x{cam['ny']} on {'all' if pix is None else len(pix)} pixels, "
          f"{oracle.max_threads()} threads")
-    So, sto, nso = oracle.render(cam, w["units"], w["model"], snap=snap, pixels=pix,
-                                 threads=oracle.max_threads())
+    if pix is None:
+        # the whole image in bands of rows, so that progress is visible
+        npix = cam["nx"] * cam["ny"]
+        band = CHUNK_ROWS * cam["nx"]
+        parts = []
+        for lo in range(0, npix, band):
+            rows = np.arange(lo, min(lo + band, npix), dtype=np.int64)
+            parts.append(oracle.render(cam, w["units"], w["model"], snap=snap, pixels=rows,
+                                       threads=oracle.max_threads()))
+            _log(f"oracle pixels {lo}..{rows[-1]} done, {time.perf_counter() - t0:.1f} s")
+        So = np.concatenate([p[0] for p in parts], axis=1)
+        sto = np.concatenate([p[1] for p in parts])
+        nso = np.concatenate([p[2] for p in parts])
+    else:
+        So, sto, nso = oracle.render(cam, w["units"], w["model"], snap=snap, pixels=pix,
+                                     threads=oracle.max_threads())
     _log(f"oracle done in {time.perf_counter() - t0:.1f} s")
     return So.reshape(4, -1), sto.reshape(-1), nso.reshape(-1)
 
