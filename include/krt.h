@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 6
+#define KRT_ABI_VERSION 7
 
 typedef enum {
     KRT_OK = 0,
@@ -319,6 +319,23 @@ krt_status krt_autotune(krt_ctx* ctx, const krt_camera* groups, int32_t ngroups,
  * KRT_E_INVAL, KRT_E_STATE (no units), KRT_E_HIP. */
 krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam,
                       double out_flux_jy[4], double* out_imax);
+
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): krt_reduce
+ * with its block partials in a fixed device scratch area of the library
+ * (73.9 KB per device: 1024 blocks x 9 doubles and the five results, one copy
+ * per device, held until the process ends; its address is looked up once per
+ * device by krt_create).  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine; results are read back through the context's
+ * pinned buffer, made by krt_create.  Any image size: the scratch's size does
+ * not depend on it.  Same results as krt_reduce, bit for bit.  All calls on one
+ * device share the scratch, which keeps the last call's contents (every value
+ * read is written first): calls that overlap on one device (other threads, or
+ * other contexts' streams) race.  Synchronises the stream.  Errors: as
+ * krt_reduce; KRT_E_UNSUPPORTED for a device index of 64 or more;
+ * KRT_E_STATE if the scratch address was not resolved. */
+krt_status krt_reduce_noalloc(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam,
+                              double out_flux_jy[4], double* out_imax);
 
 /* Message of the last error on this context (never NULL; owned by the
  * context, valid until its next call). */

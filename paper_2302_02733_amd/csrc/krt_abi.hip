@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -86,11 +87,38 @@ struct krt_ctx {
     std::string err;
 };
 
+// Device scratch of the allocation-free reduction (see kScratchDoubles below):
+// one copy per device, alive until the process ends.
+static __device__ __align__(256) double scratch[1024 * 9 + 16];
+
 namespace {
 
 constexpr int kSectors = 8;   // XCDs of the device: one image sector each
 constexpr int kWorkWords = 2 + 2 * 10 + kSectors;
 constexpr int kRedBlocks = 1024;
+
+// Scratch of the allocation-free reduction (krt_reduce_noalloc): the block
+// partials of reduce_partial (9 doubles for each of at most kRedBlocks blocks)
+// and the five results, 73.9 KB per device whatever the image size.  Host code
+// never uses the array's name as an address: each device's address comes from
+// hipGetSymbolAddress at context creation (kept in g_scratch_dev).
+constexpr size_t kScratchDoubles = (size_t)kRedBlocks * 9 + 16;
+static_assert(sizeof(scratch) == kScratchDoubles * sizeof(double), "scratch size");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Looks up this device's copy of `scratch` once (the device must be current).
+hipError_t resolve_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipSuccess;   // the entry point refuses such devices
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_dev[device] = static_cast<double*>(p);
+    return e;
+}
 
 krt_status fail(krt_ctx* ctx, krt_status code, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -654,6 +682,8 @@ krt_status krt_create(int device, krt_ctx** out) {
         e = hipGetDeviceProperties(&prop, device);
         if (e != hipSuccess) { st = hip_fail(ctx, e, "hipGetDeviceProperties"); break; }
         ctx->cu_count = prop.multiProcessorCount;
+        e = resolve_scratch(device);
+        if (e != hipSuccess) { st = hip_fail(ctx, e, "hipGetSymbolAddress(scratch)"); break; }
         if (hipMalloc(&ctx->work, kWorkWords * sizeof(unsigned)) != hipSuccess ||
             hipMalloc(&ctx->red_partial, (kRedBlocks * 9 + 16) * sizeof(double)) != hipSuccess ||
             hipMalloc(&ctx->btab, (size_t)kBesPanels * 2 * kBesCoef * sizeof(double)) != hipSuccess ||
@@ -1190,30 +1220,70 @@ krt_status krt_geodesic_only(krt_ctx* ctx, const krt_camera* cam, double* d_end_
     return KRT_OK;
 }
 
-krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam, double out_flux_jy[4],
-                      double* out_imax) {
-    if (!ctx) return KRT_E_INVAL;
-    const std::string m = check_camera(cam);
-    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
-    if (!d_stokes || !out_flux_jy || !out_imax) return fail(ctx, KRT_E_INVAL, "NULL argument");
-    if (!ctx->units_set) return fail(ctx, KRT_E_STATE, "units not set");
-    KRT_HIP(ctx, hipSetDevice(ctx->device));
+}  // extern "C"
+
+namespace {
+
+// The image reduction with its block partials and results in `partial`
+// (kScratchDoubles doubles: the context's buffer or the static scratch).
+krt_status reduce_into(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam, double out_flux_jy[4],
+                       double* out_imax, double* partial) {
     const size_t np = (size_t)cam->nx * cam->ny;
     const double L = kG * ctx->units.M_bh_g / (kC * kC);
     const double D = ctx->units.dist_cm;
     const double dOm = (cam->fov_x * L / (cam->nx * D)) * (cam->fov_y * L / (cam->ny * D));
     int nb = (int)((np + 255) / 256);
     if (nb > kRedBlocks) nb = kRedBlocks;
-    hipLaunchKernelGGL(reduce_partial, dim3(nb), dim3(256), 0, ctx->stream, d_stokes, np, ctx->red_partial);
+    // every partial read below is written first: nothing needs clearing
+    hipLaunchKernelGGL(reduce_partial, dim3(nb), dim3(256), 0, ctx->stream, d_stokes, np, partial);
     KRT_HIP(ctx, hipGetLastError());
-    double* out = ctx->red_partial + (size_t)kRedBlocks * 9;  // 16 doubles after the partials
-    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(1), 0, ctx->stream, ctx->red_partial, nb, 1e23 * dOm, out);
+    double* out = partial + (size_t)kRedBlocks * 9;  // 16 doubles after the partials
+    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(1), 0, ctx->stream, partial, nb, 1e23 * dOm, out);
     KRT_HIP(ctx, hipGetLastError());
     KRT_HIP(ctx, hipMemcpyAsync(ctx->host_buf, out, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     KRT_HIP(ctx, hipStreamSynchronize(ctx->stream));
     for (int k = 0; k < 4; ++k) out_flux_jy[k] = ctx->host_buf[k];
     *out_imax = ctx->host_buf[4];
     return KRT_OK;
+}
+
+krt_status reduce_checks(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam, double out_flux_jy[4],
+                         double* out_imax) {
+    const std::string m = check_camera(cam);
+    if (!m.empty()) return fail(ctx, KRT_E_INVAL, m);
+    if (!d_stokes || !out_flux_jy || !out_imax) return fail(ctx, KRT_E_INVAL, "NULL argument");
+    if (!ctx->units_set) return fail(ctx, KRT_E_STATE, "units not set");
+    return KRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+krt_status krt_reduce(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam, double out_flux_jy[4],
+                      double* out_imax) {
+    if (!ctx) return KRT_E_INVAL;
+    krt_status st = reduce_checks(ctx, d_stokes, cam, out_flux_jy, out_imax);
+    if (st != KRT_OK) return st;
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    return reduce_into(ctx, d_stokes, cam, out_flux_jy, out_imax, ctx->red_partial);
+}
+
+krt_status krt_reduce_noalloc(krt_ctx* ctx, const double* d_stokes, const krt_camera* cam,
+                              double out_flux_jy[4], double* out_imax) {
+    if (!ctx) return KRT_E_INVAL;
+    krt_status st = reduce_checks(ctx, d_stokes, cam, out_flux_jy, out_imax);
+    if (st != KRT_OK) return st;
+    if (ctx->device >= kMaxDevices) return fail(ctx, KRT_E_UNSUPPORTED, "device index above the scratch table");
+    static_assert((size_t)kRedBlocks * 9 + 5 <= kScratchDoubles, "scratch holds the partials and the results");
+    double* partial = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        partial = g_scratch_dev[ctx->device];
+    }
+    if (!partial) return fail(ctx, KRT_E_STATE, "static scratch of this device not resolved");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    return reduce_into(ctx, d_stokes, cam, out_flux_jy, out_imax, partial);
 }
 
 const char* krt_last_error(const krt_ctx* ctx) {

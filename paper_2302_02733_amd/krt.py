@@ -108,6 +108,8 @@ _SIGS = {
                                        ctypes.POINTER(Stats)]),
     "krt_reduce": (ctypes.c_int, [_P, _P, ctypes.POINTER(Camera), ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]),
+    "krt_reduce_noalloc": (ctypes.c_int, [_P, _P, ctypes.POINTER(Camera), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
     "krt_last_error": (ctypes.c_char_p, [_P]),
     "krt_check_camera": (ctypes.c_int, [ctypes.POINTER(Camera), ctypes.c_char_p, ctypes.c_size_t]),
     "krt_geodesic_only": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P, _P]),
