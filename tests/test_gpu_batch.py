@@ -251,3 +251,65 @@ def test_batch_rejects_bad_instances(krt):
         with pytest.raises(ValueError):     # output of the wrong size
             ctx.trace_batch(groups, [{"group": 0, "freq_hz": 230e9,
                                       "stokes": torch.empty((4, 4, 4), dtype=torch.float64, device="cuda")}])
+
+
+@pytest.mark.timeout(600)
+def test_full_library_equals_plain_and_oracle(krt):
+    """The 256-instance library on the 288x128x128 snapshot (all its
+    (inclination, resolution) groups, 128^2 to 1024^2) in one launch: every
+    instance image equals the plain tracer's to 1e-12 of its I_max, and for
+    one instance of each group 2048 seeded pixels meet the FP64 parity bar
+    against the oracle (p99 of |dS|/I_max and the sample's flux)."""
+    desc = W.snapshot_desc()
+    P = W.make_snapshot(desc, 7)
+    t = torch.tensor(P, device="cuda")
+    groups, inst = W.batch_library()
+    for d in inst:
+        g = groups[d["group"]]
+        d["stokes"] = torch.empty((4, g["ny"], g["nx"]), dtype=torch.float64, device="cuda")
+    picked = {}
+    for k, d in enumerate(inst):
+        picked.setdefault(d["group"], k)
+    with krt.Context(0) as ctx:
+        ctx.set_units(W.UNITS)
+        ctx.set_model_snapshot(desc, t)
+        _log(f"library: {len(inst)} instances in {len(groups)} groups")
+        stats = ctx.trace_batch(groups, inst)
+        torch.cuda.synchronize()
+        _log(f"library done: {stats}")
+        assert stats["rays"] == sum(groups[d["group"]]["nx"] * groups[d["group"]]["ny"] for d in inst)
+        worst = 0.0
+        samples = {}
+        for k, d in enumerate(inst):
+            g = groups[d["group"]]
+            cam = dict(g, freq_hz=d["freq_hz"])
+            Sp = torch.empty((4, g["ny"], g["nx"]), dtype=torch.float64, device="cuda")
+            ctx.set_model_snapshot(dict(desc, M_unit_g=d["M_unit_g"], R_high=d["R_high"]), t)
+            ctx.trace(cam, stokes=Sp, stats=False)
+            im = float(Sp[0].max())
+            err = float((d["stokes"] - Sp).abs().max()) / im if im > 0 else float(d["stokes"].abs().max())
+            worst = max(worst, err)
+            assert err <= SAME_TOL, (k, err)
+            if k == picked.get(d["group"]):
+                pix = W.pixel_sample(g["nx"], g["ny"], 2048, 100 + d["group"])
+                samples[k] = (pix, d["stokes"].reshape(4, -1)[:, torch.tensor(pix, device="cuda")].cpu().numpy())
+            if k % 32 == 31:
+                _log(f"instances 0..{k} equal the plain tracer (worst {worst:.2e})")
+    for k, (pix, S) in samples.items():
+        d = inst[k]
+        g = groups[d["group"]]
+        dd = dict(desc, M_unit_g=d["M_unit_g"], R_high=d["R_high"])
+        cc = dict(g, freq_hz=d["freq_hz"])
+        So, _, _ = oracle.render(cc, W.UNITS, {"kind": 3}, snap=oracle.SnapshotHandle(dd, P), pixels=pix,
+                                 threads=oracle.max_threads())
+        imax = So[0].max()
+        if imax <= 0.0:
+            assert np.abs(S).max() == 0.0
+            continue
+        p99 = max(np.percentile(np.abs(S[s] - So[s]) / imax, 99) for s in range(4))
+        dflux = max(abs(S[s].sum() - So[s].sum()) for s in range(4)) / So[0].sum()
+        worst_pix = int(np.argmax(np.abs(S - So).max(axis=0)))
+        _log(f"instance {k} (group {d['group']}, {g['nx']}^2, {g['incl_deg']} deg): p99 {p99:.2e}, "
+             f"flux {dflux:.2e}, worst pixel {pix[worst_pix]} |dS|/Imax "
+             f"{np.abs(S - So)[:, worst_pix].max() / imax:.2e}")
+        assert p99 <= P99_TOL and dflux <= FLUX_TOL
