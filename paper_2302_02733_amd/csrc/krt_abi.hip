@@ -56,6 +56,7 @@ struct krt_ctx {
     // pixel list of the measurement probe
     int32_t* probe_dev = nullptr;
     size_t probe_cap = 0;
+
     // launch configuration (tile shape, grid, slice size)
     krt_launch_config cfg{sizeof(krt_launch_config), 8, 0, 0, 1};
     // batch descriptors: device copy and pinned staging
@@ -274,7 +275,7 @@ krt_status ensure_pool(krt_ctx* ctx, bool batch = false) {
     if (per_cu < 1) per_cu = 1;
     if (ctx->cfg.blocks_per_cu > 0 && ctx->cfg.blocks_per_cu < per_cu) per_cu = ctx->cfg.blocks_per_cu;
     int blocks = per_cu * ctx->cu_count;
-    const size_t per_block = (size_t)4 * 64 * cap * 8 * sizeof(double);
+    const size_t per_block = (size_t)4 * 64 * cap * kPointDoubles * sizeof(double);
     const size_t budget = (size_t)(budget_gb * 1073741824.0);
     if ((size_t)blocks * per_block > budget) blocks = (int)(budget / per_block);
     if (blocks < 1) return fail(ctx, KRT_E_NOMEM, "path store budget too small");
@@ -317,7 +318,7 @@ krt_status ensure_chunks(krt_ctx* ctx) {
     ctx->nchunks = 0;
     ctx->chunk_cap = cap;
     if (count == 0) return KRT_OK;
-    const size_t bytes = (size_t)count * cap * 512 * sizeof(double);
+    const size_t bytes = (size_t)count * cap * 64 * kPointDoubles * sizeof(double);
     if (hipMalloc(&ctx->chunk_pool, bytes) != hipSuccess ||
         hipMalloc(&ctx->chunk_flags, (size_t)count * sizeof(unsigned)) != hipSuccess) {
         (void)hipGetLastError();
@@ -337,7 +338,7 @@ krt_status ensure_long(krt_ctx* ctx, int max_steps, size_t npix) {
             KRT_HIP(ctx, hipFree(ctx->long_pool));
             ctx->long_pool = nullptr;
         }
-        const size_t per = (size_t)(max_steps + 1) * 8 * sizeof(double);
+        const size_t per = (size_t)(max_steps + 1) * kPointDoubles * sizeof(double);
         int slots = 1024;
         while (slots > 64 && (size_t)slots * per > ((size_t)4 << 30)) slots /= 2;
         if (hipMalloc(&ctx->long_pool, (size_t)slots * per) != hipSuccess) {

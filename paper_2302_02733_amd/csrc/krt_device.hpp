@@ -60,6 +60,37 @@ KRT_HD double rsqrt_fast(double x) {
 #endif
 }
 
+// sin and cos of a polar angle th in [0, pi]: th is reduced to t in
+// [-pi/4, pi/4] around 0, pi/2 or pi (exactly, by Sterbenz's lemma, with the
+// low part of pi/2 added after), and sin t, cos t are their Taylor series
+// through t^17 and t^16 (truncation below 1e-19 for |t| <= pi/4), in Horner
+// form.  A third of the instructions of the general sincos, whose argument
+// reduction must handle any angle.
+constexpr double kInvFactSin[9] = {1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0,
+                                   -1.0 / 39916800.0, 1.0 / 6227020800.0, -1.0 / 1307674368000.0,
+                                   1.0 / 355687428096000.0};
+constexpr double kInvFactCos[9] = {1.0, -0.5, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0,
+                                   -1.0 / 3628800.0, 1.0 / 479001600.0, -1.0 / 87178291200.0,
+                                   1.0 / 20922789888000.0};
+
+KRT_HD void sincos_polar(double th, double& s, double& c) {
+    constexpr double kPio2Hi = 1.5707963267948966;      // nearest double to pi/2
+    constexpr double kPio2Lo = 6.123233995736766e-17;   // pi/2 - kPio2Hi
+    const int q = th < 0.78539816339744831 ? 0 : (th > 2.3561944901923448 ? 2 : 1);
+    const double t = (th - q * kPio2Hi) - q * kPio2Lo;
+    const double t2 = t * t;
+    double ps = kInvFactSin[8], pc = kInvFactCos[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        ps = fma(ps, t2, kInvFactSin[k]);
+        pc = fma(pc, t2, kInvFactCos[k]);
+    }
+    const double st = ps * t;   // sin t
+    // th = q pi/2 + t: (sin, cos) = (st, pc), (pc, -st), (-st, -pc)
+    s = q == 0 ? st : (q == 1 ? pc : -st);
+    c = q == 0 ? pc : (q == 1 ? -st : -pc);
+}
+
 // ---------------------------------------------------------------------------
 // Kerr-Schild metric at (r, theta): the seven non-zero covariant components,
 // their r and theta derivatives, and the six non-zero inverse components.
@@ -205,40 +236,46 @@ KRT_HD void geodesic_acc(double a, double m, double r, double th, const double K
 }
 
 // Connection along the ray A^mu_b = Gamma^mu_ab K^a =
-// 1/2 g^{mu nu} [M_{nu b} + delta_b^r (D_r K)_nu + delta_b^h (D_h K)_nu
-//               - delta_nu^r (D_r K)_b - delta_nu^h (D_h K)_b],
-// M = K^r D_r g + K^h D_h g.  A is returned row-major, A[mu][b].
+// 1/2 g^{mu nu} T_{nu b},  T_{nu b} = M_{nu b} + delta_b^r (D_r K)_nu + delta_b^h (D_h K)_nu
+//                                    - delta_nu^r (D_r K)_b - delta_nu^h (D_h K)_b,
+// M = K^r D_r g + K^h D_h g.  Written out entry by entry: the Kerr-Schild
+// metric and its derivatives have no (t,h), (r,h) or (h,p) components, so
+// T_rr = M_rr and T_hh = M_hh, and each sum runs over the non-zero terms only
+// (a product with a structural zero is not free in IEEE arithmetic).
+// A is returned row-major, A[mu][b].
 KRT_HD void connection(const Metric& g, const MetricD& dr, const MetricD& dh, const double K[4],
                        double A[16]) {
     double vr[4], vh[4];
     dmetric_times(dr, K, vr);
     dmetric_times(dh, K, vh);
     const double kr = K[1], kh = K[2];
-    double T[16];
-    // symmetric part M
     const double Mtt = kr * dr.tt + kh * dh.tt, Mtr = kr * dr.tr + kh * dh.tr;
     const double Mtp = kr * dr.tp + kh * dh.tp, Mrr = kr * dr.rr + kh * dh.rr;
     const double Mrp = kr * dr.rp + kh * dh.rp, Mhh = kr * dr.hh + kh * dh.hh;
     const double Mpp = kr * dr.pp + kh * dh.pp;
-    T[0] = Mtt;  T[1] = Mtr;  T[2] = 0.0;  T[3] = Mtp;
-    T[4] = Mtr;  T[5] = Mrr;  T[6] = 0.0;  T[7] = Mrp;
-    T[8] = 0.0;  T[9] = 0.0;  T[10] = Mhh; T[11] = 0.0;
-    T[12] = Mtp; T[13] = Mrp; T[14] = 0.0; T[15] = Mpp;
-    for (int nu = 0; nu < 4; ++nu) {
-        T[nu * 4 + 1] += vr[nu];
-        T[nu * 4 + 2] += vh[nu];
-    }
-    for (int b = 0; b < 4; ++b) {
-        T[1 * 4 + b] -= vr[b];
-        T[2 * 4 + b] -= vh[b];
-    }
-    for (int b = 0; b < 4; ++b) {
-        const double t0 = T[b], t1 = T[4 + b], t2 = T[8 + b], t3 = T[12 + b];
-        A[0 * 4 + b] = 0.5 * (g.Itt * t0 + g.Itr * t1);
-        A[1 * 4 + b] = 0.5 * (g.Itr * t0 + g.Irr * t1 + g.Irp * t3);
-        A[2 * 4 + b] = 0.5 * (g.Ihh * t2);
-        A[3 * 4 + b] = 0.5 * (g.Irp * t1 + g.Ipp * t3);
-    }
+    // T rows t, r, h, p (columns t, r, h, p)
+    const double Ttt = Mtt, Ttr = Mtr + vr[0], Tth = vh[0], Ttp = Mtp;
+    const double Trt = Mtr - vr[0], Trr = Mrr, Trh = vh[1] - vr[2], Trp = Mrp - vr[3];
+    const double Tht = -vh[0], Thr = vr[2] - vh[1], Thh = Mhh, Thp = -vh[3];
+    const double Tpt = Mtp, Tpr = Mrp + vr[3], Tph = vh[3], Tpp = Mpp;
+    const double htt = 0.5 * g.Itt, htr = 0.5 * g.Itr, hrr = 0.5 * g.Irr, hrp = 0.5 * g.Irp;
+    const double hhh = 0.5 * g.Ihh, hpp = 0.5 * g.Ipp;
+    A[0] = htt * Ttt + htr * Trt;
+    A[1] = htt * Ttr + htr * Trr;
+    A[2] = htt * Tth + htr * Trh;
+    A[3] = htt * Ttp + htr * Trp;
+    A[4] = htr * Ttt + hrr * Trt + hrp * Tpt;
+    A[5] = htr * Ttr + hrr * Trr + hrp * Tpr;
+    A[6] = htr * Tth + hrr * Trh + hrp * Tph;
+    A[7] = htr * Ttp + hrr * Trp + hrp * Tpp;
+    A[8] = hhh * Tht;
+    A[9] = hhh * Thr;
+    A[10] = hhh * Thh;
+    A[11] = hhh * Thp;
+    A[12] = hrp * Trt + hpp * Tpt;
+    A[13] = hrp * Trr + hpp * Tpr;
+    A[14] = hrp * Trh + hpp * Tph;
+    A[15] = hrp * Trp + hpp * Tpp;
 }
 
 // ---------------------------------------------------------------------------
@@ -518,16 +555,47 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
 
 // ---------------------------------------------------------------------------
 // Bessel-function ratios K0/K2 and K1/K2 of x = 1/Theta_e.
-// Table: piecewise Chebyshev series in t = ln x over [ln 1e-8, ln 700],
-// kBesPanels panels of degree kBesDeg, built at context creation from the
-// trapezoid rule on K_nu(x) e^x = int_0^inf exp(-x (cosh s - 1)) cosh(nu s) ds.
-// Outside: leading small-x forms below 1e-8, the asymptotic series above 700.
+// Table: piecewise Chebyshev series of degree kBesDeg in x itself, on panels
+// that split every binade [2^e, 2^(e+1)) of [2^kBesE0, 2^kBesE1) into
+// kBesSub equal parts, built at context creation from the trapezoid rule on
+// K_nu(x) e^x = int_0^inf exp(-x (cosh s - 1)) cosh(nu s) ds.  A panel and
+// its Chebyshev variable come from the exponent and mantissa bits of x (no
+// logarithm); the ratios are analytic in x away from x = 0, which lies 8 panel
+// half-widths or more from every panel, so degree 12 reaches round-off.
+// Outside [1e-8, 700]: leading small-x forms, the asymptotic series above.
 // ---------------------------------------------------------------------------
-constexpr int kBesPanels = 64;
-constexpr int kBesDeg = 14;
+constexpr int kBesE0 = -27;                      // 2^-27 < 1e-8
+constexpr int kBesE1 = 10;                       // 2^10 > 700
+constexpr int kBesSub = 4;                       // panels per binade
+constexpr int kBesPanels = (kBesE1 - kBesE0) * kBesSub;
+constexpr int kBesDeg = 12;
 constexpr int kBesCoef = kBesDeg + 1;
-constexpr double kBesT0 = -18.420680743952367;   // ln 1e-8
-constexpr double kBesT1 = 6.551080335043404;     // ln 700
+
+// Panel of x in [2^kBesE0, 2^kBesE1) and the Chebyshev variable z in [-1, 1]
+// there: x = m 2^e with m in [1, 2); sub-panel k = floor(4 (m - 1)) (the top two
+// mantissa bits); z = 8 (m - 1) - (2 k + 1).
+KRT_HD int bessel_panel(double x, double& z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int hi = __double2hiint(x);
+    const int e = ((hi >> 20) & 0x7ff) - 1023;
+    const int k = (hi >> 18) & (kBesSub - 1);
+    const double m = __hiloint2double((hi & 0x000fffff) | 0x3ff00000, __double2loint(x));
+#else
+    int e;
+    const double m = 2.0 * frexp(x, &e);
+    e -= 1;
+    const int k = (int)((m - 1.0) * kBesSub);
+#endif
+    z = 8.0 * m - (double)(9 + 2 * k);
+    int p = (e - kBesE0) * kBesSub + k;
+    return p < 0 ? 0 : (p >= kBesPanels ? kBesPanels - 1 : p);
+}
+
+// x at Chebyshev variable z of panel p (table construction).
+KRT_HD double bessel_panel_x(int p, double z) {
+    const int e = kBesE0 + p / kBesSub, k = p % kBesSub;
+    return ldexp(1.0 + (2 * k + 1 + z) * 0.125, e);
+}
 
 // Asymptotic series of sqrt(2x/pi) e^x K_nu(x) for large x.
 KRT_HD double bessel_k_asym_series(double nu, double x) {
@@ -555,26 +623,23 @@ KRT_HD void bessel_ratios(const double* __restrict__ table, double x,
         k1k2 = 0.5 * x;
         return;
     }
-    const double t = log(x);
-    const double width = (kBesT1 - kBesT0) / kBesPanels;
-    int p = (int)((t - kBesT0) / width);
-    p = p < 0 ? 0 : (p >= kBesPanels ? kBesPanels - 1 : p);
-    const double mid = kBesT0 + (p + 0.5) * width;
-    const double z = (t - mid) * (2.0 / width);
+    double z;
+    const int p = bessel_panel(x, z);
     const double* c0 = table + (size_t)p * 2 * kBesCoef;
     const double* c1 = c0 + kBesCoef;
     // Clenshaw recurrences
-    double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
-    for (int k = kBesDeg; k >= 1; --k) {
-        const double bt = 2.0 * z * b1 - b2 + c0[k];
+    const double z2 = 2.0 * z;
+    double b1 = c0[kBesDeg], b2 = 0.0, d1 = c1[kBesDeg], d2 = 0.0;
+    for (int k = kBesDeg - 1; k >= 1; --k) {
+        const double bt = fma(z2, b1, c0[k] - b2);
         b2 = b1;
         b1 = bt;
-        const double dt = 2.0 * z * d1 - d2 + c1[k];
+        const double dt = fma(z2, d1, c1[k] - d2);
         d2 = d1;
         d1 = dt;
     }
-    k0k2 = z * b1 - b2 + c0[0];
-    k1k2 = z * d1 - d2 + c1[0];
+    k0k2 = fma(z, b1, c0[0] - b2);
+    k1k2 = fma(z, d1, c1[0] - d2);
 }
 
 // ---------------------------------------------------------------------------
@@ -670,13 +735,13 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
 // d_k = e^-tau c_k, with 1 - d0 = -expm1(-tau) + e^-tau (1 - c0) free of
 // cancellation.
 // ---------------------------------------------------------------------------
-// G v with G = -w K'; K' rows (0, AQ, 0, AV), (AQ, 0, RV, 0), (0, -RV, 0, RQ), (AV, 0, -RQ, 0).
-KRT_HD void gen_apply(double AQ, double AV, double RQ, double RV, double w, const double v[4],
-                      double o[4]) {
-    o[0] = -w * (AQ * v[1] + AV * v[3]);
-    o[1] = -w * (AQ * v[0] + RV * v[2]);
-    o[2] = -w * (-RV * v[1] + RQ * v[3]);
-    o[3] = -w * (AV * v[0] - RQ * v[2]);
+// G v with G = -w K'; K' rows (0, AQ, 0, AV), (AQ, 0, RV, 0), (0, -RV, 0, RQ), (AV, 0, -RQ, 0);
+// called with the w-scaled entries gQ = -w AQ, gV = -w AV, hQ = -w RQ, hV = -w RV.
+KRT_HD void gen_apply(double gQ, double gV, double hQ, double hV, const double v[4], double o[4]) {
+    o[0] = gQ * v[1] + gV * v[3];
+    o[1] = gQ * v[0] + hV * v[2];
+    o[2] = hQ * v[3] - hV * v[1];
+    o[3] = gV * v[0] - hQ * v[2];
 }
 
 // 1/n! for n = 0..21 (correctly rounded).
@@ -759,12 +824,13 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
     }
     double D[4] = {S[0] - Seq, S[1], S[2], S[3]};
     double T[4], U[4];
+    const double gQ = -w * AQ, gV = -w * AV, hQ = -w * RQ, hV = -w * RV;
     for (int k = 0; k < 4; ++k) T[k] = d3 * D[k];
-    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    gen_apply(gQ, gV, hQ, hV, T, U);
     for (int k = 0; k < 4; ++k) T[k] = d2 * D[k] + U[k];
-    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    gen_apply(gQ, gV, hQ, hV, T, U);
     for (int k = 0; k < 4; ++k) T[k] = d1 * D[k] + U[k];
-    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    gen_apply(gQ, gV, hQ, hV, T, U);
     S[0] = d0 * S[0] + omd0 * Seq + U[0];
     S[1] = d0 * S[1] + U[1];
     S[2] = d0 * S[2] + U[2];
@@ -791,24 +857,36 @@ KRT_HD double ni(const Coh& N, int i, int j) {
     return (i == j) ? 0.0 : ((i < j) ? N.I[asym_idx(i, j)] : -N.I[asym_idx(j, i)]);
 }
 
-// F(A, N) = -(A N + N A^T).
+// F(A, N) = -(A N + N A^T), entry by entry as one chain of fused
+// multiply-adds over the non-zero terms (the imaginary part has a zero
+// diagonal); the chain starts from its first product, not from 0.
 KRT_HD void transport_rhs(const double A[16], const Coh& N, Coh& F) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = i; j < 4; ++j) {
-            double s = 0.0;
+            double s = A[i * 4] * nr(N, 0, j);
+            s = fma(nr(N, i, 0), A[j * 4], s);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) s += A[i * 4 + b] * nr(N, b, j) + nr(N, i, b) * A[j * 4 + b];
+            for (int b = 1; b < 4; ++b) {
+                s = fma(A[i * 4 + b], nr(N, b, j), s);
+                s = fma(nr(N, i, b), A[j * 4 + b], s);
+            }
             F.R[sym_idx(i, j)] = -s;
         }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = i + 1; j < 4; ++j) {
-            double s = 0.0;
+            // A_ib N_bj (b != j) + N_ib A_jb (b != i); the first term is b = 0
+            // or, for i = 0, b = 1 (j >= 1, so b = 0 != j)
+            double s = A[i * 4] * ni(N, 0, j);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) s += A[i * 4 + b] * ni(N, b, j) + ni(N, i, b) * A[j * 4 + b];
+            for (int b = 1; b < 4; ++b)
+                if (b != j) s = fma(A[i * 4 + b], ni(N, b, j), s);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b != i) s = fma(ni(N, i, b), A[j * 4 + b], s);
             F.I[asym_idx(i, j)] = -s;
         }
 }
@@ -824,7 +902,7 @@ KRT_HD void coh_project(const Coh& N, const double l1[4], const double l2[4], do
         for (int j = 0; j < 4; ++j) {
             y1 += nr(N, i, j) * l1[j];
             y2 += nr(N, i, j) * l2[j];
-            z2 += ni(N, i, j) * l2[j];
+            if (j != i) z2 += ni(N, i, j) * l2[j];
         }
         n11 += l1[i] * y1;
         n12 += l1[i] * y2;
@@ -838,18 +916,27 @@ KRT_HD void coh_project(const Coh& N, const double l1[4], const double l2[4], do
 }
 
 // N from Stokes on two legs given as vectors e1, e2.
+// N = n11 e1 e1 + n22 e2 e2 + nre (e1 e2 + e2 e1) + i nim (e1 e2 - e2 e1),
+// as N^ij = e1^i p^j + e2^i q^j with p = n11 e1 + nre e2, q = n22 e2 + nre e1.
 KRT_HD void coh_rebuild(Coh& N, const double S[4], const double e1[4], const double e2[4]) {
     const double n11 = 0.5 * (S[0] + S[1]), n22 = 0.5 * (S[0] - S[1]);
     const double nre = 0.5 * S[2], nim = -0.5 * S[3];
+    double p[4], q[4], r1[4], r2[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        p[j] = n11 * e1[j] + nre * e2[j];
+        q[j] = n22 * e2[j] + nre * e1[j];
+        r1[j] = nim * e1[j];
+        r2[j] = nim * e2[j];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = i; j < 4; ++j)
-            N.R[sym_idx(i, j)] = n11 * e1[i] * e1[j] + n22 * e2[i] * e2[j] + nre * (e1[i] * e2[j] + e2[i] * e1[j]);
+        for (int j = i; j < 4; ++j) N.R[sym_idx(i, j)] = e1[i] * p[j] + e2[i] * q[j];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = i + 1; j < 4; ++j) N.I[asym_idx(i, j)] = nim * (e1[i] * e2[j] - e2[i] * e1[j]);
+        for (int j = i + 1; j < 4; ++j) N.I[asym_idx(i, j)] = e1[i] * r2[j] - e2[i] * r1[j];
 }
 
 // ---------------------------------------------------------------------------

@@ -124,30 +124,33 @@ KRT_HD void connection_f(const MetricF& g, const MetricDF& dr, const MetricDF& d
     vh[2] = dh.hh * K[2];
     vh[3] = dh.tp * K[0] + dh.rp * K[1] + dh.pp * K[3];
     const float kr = K[1], kh = K[2];
-    float T[16];
     const float Mtt = kr * dr.tt + kh * dh.tt, Mtr = kr * dr.tr + kh * dh.tr;
     const float Mtp = kr * dr.tp + kh * dh.tp, Mrr = kr * dr.rr + kh * dh.rr;
     const float Mrp = kr * dr.rp + kh * dh.rp, Mhh = kr * dr.hh + kh * dh.hh;
     const float Mpp = kr * dr.pp + kh * dh.pp;
-    T[0] = Mtt;  T[1] = Mtr;  T[2] = 0.0f;  T[3] = Mtp;
-    T[4] = Mtr;  T[5] = Mrr;  T[6] = 0.0f;  T[7] = Mrp;
-    T[8] = 0.0f; T[9] = 0.0f; T[10] = Mhh;  T[11] = 0.0f;
-    T[12] = Mtp; T[13] = Mrp; T[14] = 0.0f; T[15] = Mpp;
-    for (int nu = 0; nu < 4; ++nu) {
-        T[nu * 4 + 1] += vr[nu];
-        T[nu * 4 + 2] += vh[nu];
-    }
-    for (int b = 0; b < 4; ++b) {
-        T[4 + b] -= vr[b];
-        T[8 + b] -= vh[b];
-    }
-    for (int b = 0; b < 4; ++b) {
-        const float t0 = T[b], t1 = T[4 + b], t2 = T[8 + b], t3 = T[12 + b];
-        A[b] = 0.5f * (g.Itt * t0 + g.Itr * t1);
-        A[4 + b] = 0.5f * (g.Itr * t0 + g.Irr * t1 + g.Irp * t3);
-        A[8 + b] = 0.5f * (g.Ihh * t2);
-        A[12 + b] = 0.5f * (g.Irp * t1 + g.Ipp * t3);
-    }
+    // T_{nu b} entry by entry over the non-zero terms (as the FP64 connection)
+    const float Ttt = Mtt, Ttr = Mtr + vr[0], Tth = vh[0], Ttp = Mtp;
+    const float Trt = Mtr - vr[0], Trr = Mrr, Trh = vh[1] - vr[2], Trp = Mrp - vr[3];
+    const float Tht = -vh[0], Thr = vr[2] - vh[1], Thh = Mhh, Thp = -vh[3];
+    const float Tpt = Mtp, Tpr = Mrp + vr[3], Tph = vh[3], Tpp = Mpp;
+    const float htt = 0.5f * g.Itt, htr = 0.5f * g.Itr, hrr = 0.5f * g.Irr, hrp = 0.5f * g.Irp;
+    const float hhh = 0.5f * g.Ihh, hpp = 0.5f * g.Ipp;
+    A[0] = htt * Ttt + htr * Trt;
+    A[1] = htt * Ttr + htr * Trr;
+    A[2] = htt * Tth + htr * Trh;
+    A[3] = htt * Ttp + htr * Trp;
+    A[4] = htr * Ttt + hrr * Trt + hrp * Tpt;
+    A[5] = htr * Ttr + hrr * Trr + hrp * Tpr;
+    A[6] = htr * Tth + hrr * Trh + hrp * Tph;
+    A[7] = htr * Ttp + hrr * Trp + hrp * Tpp;
+    A[8] = hhh * Tht;
+    A[9] = hhh * Thr;
+    A[10] = hhh * Thh;
+    A[11] = hhh * Thp;
+    A[12] = hrp * Trt + hpp * Tpt;
+    A[13] = hrp * Trr + hpp * Tpr;
+    A[14] = hrp * Trh + hpp * Tph;
+    A[15] = hrp * Trp + hpp * Tpp;
 }
 
 struct PlasmaF {
@@ -300,25 +303,28 @@ KRT_HD void bessel_ratios_f(const float* __restrict__ tab, float x, float& k0k2,
         k1k2 = 0.5f * x;
         return;
     }
-    const float t = logf(x);
-    const float width = (float)((kBesT1 - kBesT0) / kBesPanels);
-    int pn = (int)((t - (float)kBesT0) / width);
+    // panel and Chebyshev variable from the bits of x (as bessel_panel)
+    const int bits = __float_as_int(x);
+    const int e = ((bits >> 23) & 0xff) - 127;
+    const int k = (bits >> 21) & (kBesSub - 1);
+    const float m = __int_as_float((bits & 0x007fffff) | 0x3f800000);
+    const float z = 8.0f * m - (float)(9 + 2 * k);
+    int pn = (e - kBesE0) * kBesSub + k;
     pn = pn < 0 ? 0 : (pn >= kBesPanels ? kBesPanels - 1 : pn);
-    const float mid = (float)kBesT0 + (pn + 0.5f) * width;
-    const float z = (t - mid) * (2.0f / width);
     const float* c0 = tab + pn * 2 * kBesCoef;
     const float* c1 = c0 + kBesCoef;
-    float b1 = 0.0f, b2 = 0.0f, d1 = 0.0f, d2 = 0.0f;
-    for (int k = kBesDeg; k >= 1; --k) {
-        const float bt = 2.0f * z * b1 - b2 + c0[k];
+    const float z2 = 2.0f * z;
+    float b1 = c0[kBesDeg], b2 = 0.0f, d1 = c1[kBesDeg], d2 = 0.0f;
+    for (int kk = kBesDeg - 1; kk >= 1; --kk) {
+        const float bt = fmaf(z2, b1, c0[kk] - b2);
         b2 = b1;
         b1 = bt;
-        const float dt = 2.0f * z * d1 - d2 + c1[k];
+        const float dt = fmaf(z2, d1, c1[kk] - d2);
         d2 = d1;
         d1 = dt;
     }
-    k0k2 = z * b1 - b2 + c0[0];
-    k1k2 = z * d1 - d2 + c1[0];
+    k0k2 = fmaf(z, b1, c0[0] - b2);
+    k1k2 = fmaf(z, d1, c1[0] - d2);
 }
 
 // Thermal coefficients in FP32 at redshift factor g = nu / nu_cam.  Writes
@@ -519,24 +525,33 @@ KRT_HD void to_scaled_f(const Coh& N, CohF& F) {
     for (int k = 0; k < 6; ++k) F.I[k] = (float)(N.I[k] * kIScale);
 }
 
-// dN/dlam = -(A N + N A^T) for the scaled FP32 matrix.
+// dN/dlam = -(A N + N A^T) for the scaled FP32 matrix, entry by entry as one
+// fused multiply-add chain over the non-zero terms (as transport_rhs).
 KRT_HD void transport_rhs_f(const float A[16], const CohF& N, CohF& F) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = i; j < 4; ++j) {
-            float s = 0.0f;
+            float s = A[i * 4] * nrf(N, 0, j);
+            s = fmaf(nrf(N, i, 0), A[j * 4], s);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) s += A[i * 4 + b] * nrf(N, b, j) + nrf(N, i, b) * A[j * 4 + b];
+            for (int b = 1; b < 4; ++b) {
+                s = fmaf(A[i * 4 + b], nrf(N, b, j), s);
+                s = fmaf(nrf(N, i, b), A[j * 4 + b], s);
+            }
             F.R[sym_idx(i, j)] = -s;
         }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = i + 1; j < 4; ++j) {
-            float s = 0.0f;
+            float s = A[i * 4] * nif(N, 0, j);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) s += A[i * 4 + b] * nif(N, b, j) + nif(N, i, b) * A[j * 4 + b];
+            for (int b = 1; b < 4; ++b)
+                if (b != j) s = fmaf(A[i * 4 + b], nif(N, b, j), s);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b != i) s = fmaf(nif(N, i, b), A[j * 4 + b], s);
             F.I[asym_idx(i, j)] = -s;
         }
 }
@@ -550,7 +565,7 @@ KRT_HD void coh_project_f(const CohF& N, const float l1[4], const float l2[4], f
         for (int j = 0; j < 4; ++j) {
             y1 += nrf(N, i, j) * l1[j];
             y2 += nrf(N, i, j) * l2[j];
-            z2 += nif(N, i, j) * l2[j];
+            if (j != i) z2 += nif(N, i, j) * l2[j];
         }
         n11 += l1[i] * y1;
         n12 += l1[i] * y2;
@@ -565,20 +580,29 @@ KRT_HD void coh_project_f(const CohF& N, const float l1[4], const float l2[4], f
 
 // N += (coherency matrix of the Stokes increment dS on legs e1, e2) / 2^160,
 // formed in FP32 and added in FP64.
+// (dN^ij = e1^i p^j + e2^i q^j with p = n11 e1 + nre e2, q = n22 e2 + nre e1,
+// as coh_rebuild.)
 KRT_HD void coh_add_delta_f(Coh& N, const float dS[4], const float e1[4], const float e2[4]) {
     const float n11 = 0.5f * (dS[0] + dS[1]), n22 = 0.5f * (dS[0] - dS[1]);
     const float nre = 0.5f * dS[2], nim = -0.5f * dS[3];
+    float p[4], q[4], r1[4], r2[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        p[j] = n11 * e1[j] + nre * e2[j];
+        q[j] = n22 * e2[j] + nre * e1[j];
+        r1[j] = nim * e1[j];
+        r2[j] = nim * e2[j];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = i; j < 4; ++j)
-            N.R[sym_idx(i, j)] += kIScaleInv * (double)(n11 * e1[i] * e1[j] + n22 * e2[i] * e2[j] +
-                                                        nre * (e1[i] * e2[j] + e2[i] * e1[j]));
+            N.R[sym_idx(i, j)] += kIScaleInv * (double)(e1[i] * p[j] + e2[i] * q[j]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = i + 1; j < 4; ++j)
-            N.I[asym_idx(i, j)] += kIScaleInv * (double)(nim * (e1[i] * e2[j] - e2[i] * e1[j]));
+            N.I[asym_idx(i, j)] += kIScaleInv * (double)(e1[i] * r2[j] - e2[i] * r1[j]);
 }
 
 }  // namespace krt

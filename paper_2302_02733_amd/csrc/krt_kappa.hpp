@@ -397,12 +397,13 @@ KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double A
     // S' = (d0 + G(d1 + G(d2 + G d3))) S + w (b0 + G(b1 + G(b2 + G b3))) J
     const double J[4] = {JI * w, JQ * w, 0.0, JV * w};
     double T[4], U[4];
+    const double gQ = -w * AQ, gV = -w * AV, hQ = -w * RQ, hV = -w * RV;
     for (int k = 0; k < 4; ++k) T[k] = d3 * S[k] + b3 * J[k];
-    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    gen_apply(gQ, gV, hQ, hV, T, U);
     for (int k = 0; k < 4; ++k) T[k] = d2 * S[k] + b2 * J[k] + U[k];
-    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    gen_apply(gQ, gV, hQ, hV, T, U);
     for (int k = 0; k < 4; ++k) T[k] = d1 * S[k] + b1 * J[k] + U[k];
-    gen_apply(AQ, AV, RQ, RV, w, T, U);
+    gen_apply(gQ, gV, hQ, hV, T, U);
     for (int k = 0; k < 4; ++k) S[k] = d0 * S[k] + b0 * J[k] + U[k];
 }
 

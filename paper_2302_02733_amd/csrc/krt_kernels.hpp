@@ -205,6 +205,10 @@ KRT_HD void geodesic_invariants(double a, double m, const double y[7], double c[
     c[3] = (K[0] * Kl[0] + K[1] * Kl[1] + K[2] * Kl[2] + K[3] * Kl[3]) / (K[0] * K[0]);
 }
 
+// A stored point: r, theta, phi, K^t, K^r, K^theta, K^phi and the step dlam
+// that reached it (64 B).
+constexpr int kPointDoubles = 8;
+
 KRT_HD void store_point(double* p, const double y[7], double h) {
     double2* q = reinterpret_cast<double2*>(p);
     q[0] = make_double2(y[0], y[1]);
@@ -213,7 +217,7 @@ KRT_HD void store_point(double* p, const double y[7], double h) {
     q[3] = make_double2(y[6], h);
 }
 
-KRT_HD void load_point(const double* p, double v[8]) {
+KRT_HD void load_point(const double* p, double v[kPointDoubles]) {
     const double2* q = reinterpret_cast<const double2*>(p);
     const double2 a = q[0], b = q[1], c = q[2], d = q[3];
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
@@ -314,14 +318,16 @@ KRT_HD double poison_nan() { return __builtin_nan(""); }
 
 // Processes stored point n (first: the far end of the path).  On return N
 // holds the coherency matrix at the point after its radiative update.
-KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
+KRT_HD void transfer_point(const TraceArgs& A, const double pt[kPointDoubles], int n,
                                                bool first, XferState& st, Coh& N) {
     const double r = pt[0], th = pt[1], ph = pt[2];
     const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
     const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
     Metric g;
     MetricD dr, dh;
-    metric_eval_d(A.cam.a, A.cam.m, r, th, g, dr, dh);
+    double sn, cs;
+    sincos_polar(th, sn, cs);
+    metric_eval_d_sc(A.cam.a, A.cam.m, r, sn, cs, g, dr, dh);
     double Ac[16];
     connection(g, dr, dh, K, Ac);
     double Dnext = 0.0;
@@ -395,11 +401,13 @@ KRT_HD void transfer_point(const TraceArgs& A, const double pt[8], int n,
 // Fluid-frame inputs of the kappa coefficients at a stored point; returns the
 // plasma_at result (1: plasma in p, nu and cth set; 0: none, the update leaves
 // N unchanged; 2: non-finite data, the update poisons the ray).
-KRT_HD int kappa_point(const TraceArgs& A, const double pt[8], Plasma& p, double& nu, double& cth) {
+KRT_HD int kappa_point(const TraceArgs& A, const double pt[kPointDoubles], Plasma& p, double& nu, double& cth) {
     const double r = pt[0], th = pt[1], ph = pt[2];
     const double K[4] = {pt[3], pt[4], pt[5], pt[6]};
     Metric g;
-    metric_eval(A.cam.a, A.cam.m, r, th, g);
+    double sn, cs;
+    sincos_polar(th, sn, cs);
+    metric_eval_sc(A.cam.a, A.cam.m, r, sn, cs, g);
     const int pk = plasma_at(A, r, th, ph, g, p);
     if (pk != 1) return pk;
     double Kl[4];
@@ -415,7 +423,7 @@ KRT_HD int kappa_point(const TraceArgs& A, const double pt[8], Plasma& p, double
 // integrals I_in when use_in, else from the exact integrator (counted in
 // n_exact); the update is the general constant-coefficient one.  pre: the
 // plasma at the point when already evaluated, pre_kind its plasma_at result.
-KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, bool first, XferState& st,
+KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[kPointDoubles], int n, bool first, XferState& st,
                                  Coh& N, const double* I_in, bool use_in, unsigned& n_exact,
                                  const Plasma* pre = nullptr, int pre_kind = 0) {
     const double r = pt[0], th = pt[1], ph = pt[2];
@@ -423,7 +431,9 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
     const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
     Metric g;
     MetricD dr, dh;
-    metric_eval_d(A.cam.a, A.cam.m, r, th, g, dr, dh);
+    double sn, cs;
+    sincos_polar(th, sn, cs);
+    metric_eval_d_sc(A.cam.a, A.cam.m, r, sn, cs, g, dr, dh);
     double Ac[16];
     connection(g, dr, dh, K, Ac);
     double Dnext = 0.0;
@@ -504,7 +514,7 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[8], int n, 
 // FP32, the coherency matrix and the Heun state in FP64, every increment
 // formed in FP32 (scaled by 2^160) and added in FP64.  The radiative update
 // adds the coherency matrix of the Stokes increment on the fluid legs.
-KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[8], int n, bool first,
+KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles], int n, bool first,
                                XferStateF& st, Coh& N) {
     const F32Consts& C = A.f32;
     // sin and cos of theta from an argument reduced in FP64 toward the nearer pole
@@ -678,10 +688,11 @@ __device__ __forceinline__ int take_chunk(const TraceArgs& A, int* wchunks, int 
 // the wave's chunks in the order taken.
 __device__ __forceinline__ const double* point_addr(const TraceArgs& A, const double* slot,
                                                    const int* wchunks, int m, int lane) {
-    if (m < A.cap) return slot + ((size_t)m * 64 + lane) * 8;
+    if (m < A.cap) return slot + ((size_t)m * 64 + lane) * kPointDoubles;
     const int k = m / A.cap - 1;
     const int c = wchunks[k];
-    return A.chunk_pool + (size_t)c * A.cap * 512 + ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * 8;
+    return A.chunk_pool + (size_t)c * A.cap * 64 * kPointDoubles +
+           ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * kPointDoubles;
 }
 
 // Surrogate and exact-integrator point counts of a wave, added once per tile.
@@ -732,7 +743,7 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
     // stored point one point ahead; in the thermal modes, with two or three
     // waves per SIMD covering the load, it gains nothing.
     constexpr bool kPrefetch = kMode == kModeKapExact;
-    double nxt[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double nxt[kPointDoubles] = {};
     if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr(src(), slot, wchunks, nmax, lane), nxt);
     for (int m = nmax; m >= 0; --m) {
         const TraceArgs A = src();
@@ -745,7 +756,7 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
             double Xp = 0.0;
             Plasma p;
             if (m <= n_end) {
-                double pt[8];
+                double pt[kPointDoubles];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 double nu, cth, sth;
                 pk = kappa_point(A, pt, p, nu, cth);
@@ -764,27 +775,27 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
             // point at a time with the whole wave on its quadrature nodes
             unsigned long long fb = __ballot(fall);
             while (fb != 0ull) {
-                const int src = __ffsll(fb) - 1;
+                const int srcl = __ffsll(fb) - 1;
                 fb &= fb - 1ull;
-                const double w_s = __shfl(p.thetae, src), X_s = __shfl(Xp, src);
+                const double w_s = __shfl(p.thetae, srcl), X_s = __shfl(Xp, srcl);
                 double Iw[8];
                 kappa_integrals_wave(A.syntab, A.kappa, w_s, X_s, Iw);
-                if (lane == src)
+                if (lane == srcl)
                     for (int k = 0; k < 8; ++k) I[k] = Iw[k];
             }
             if (m <= n_end) {
-                double pt[8];
+                double pt[kPointDoubles];
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 n_mlp += want ? 1u : 0u;
                 n_exact += fall ? 1u : 0u;
                 transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, pk);
             }
         } else {
-            double pt[8];
+            double pt[kPointDoubles];
             if constexpr (kPrefetch) {
                 // the next point (m - 1) is loaded while this one is processed
 #pragma unroll
-                for (int k = 0; k < 8; ++k) pt[k] = nxt[k];
+                for (int k = 0; k < kPointDoubles; ++k) pt[k] = nxt[k];
                 if (m >= 1 && m - 1 <= n_end) load_point(point_addr(A, slot, wchunks, m - 1, lane), nxt);
                 if (m > n_end) continue;
             } else {
@@ -841,7 +852,7 @@ __device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i,
     }
     double sn, cs;
     sincos(y[1], &sn, &cs);
-    if (kStore && valid) store_point(slot + (size_t)lane * 8, y, 0.0);
+    if (kStore && valid) store_point(slot + (size_t)lane * kPointDoubles, y, 0.0);
 
     st = valid ? kRunning : kEscaped;
     n = 0;
@@ -867,9 +878,9 @@ __device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i,
                 }
                 ++nch;
                 cstart += A.cap;
-                cbase = A.chunk_pool + (size_t)id * A.cap * 512;
+                cbase = A.chunk_pool + (size_t)id * A.cap * 64 * kPointDoubles;
             }
-            store_point(cbase + ((size_t)(n - cstart) * 64 + lane) * 8, y, h);
+            store_point(cbase + ((size_t)(n - cstart) * 64 + lane) * kPointDoubles, y, h);
         }
         st = stop_test(A, y, h, n, sn);
     }
@@ -902,9 +913,9 @@ __device__ __forceinline__ void stage_table(TraceArgs& A, double* s_btab, float*
 // operators, or (kModeGeo) the geodesic phase only, writing the end state (no
 // store, no transfer).  Two waves per SIMD (at most 256 registers per lane):
 // with one, the FP64 dependency chains of a single wave leave the vector ALU
-// idle.  The FP32-operator mode (162 registers) runs three; the FP64 mode
-// (256) would spill heavily at the 168 that three allow.  The kappa modes
-// run one.
+// idle.  The FP32-operator mode (fewer than 168 registers) runs three; the
+// FP64 mode (256) would spill heavily at the 168 that three allow.  The kappa
+// modes run one.
 // ---------------------------------------------------------------------------
 template <int kMode>
 __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2)) void trace_waves(TraceArgs A) {
@@ -939,7 +950,7 @@ __global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2
     for (;;) {
         const TraceArgs A = src();
         const int nsec = A.nsec;
-        double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
+        double* slot = A.pool + wave * (size_t)A.cap * 64 * kPointDoubles;
         // One queue ticket per wave, taken without a lane-divergent branch:
         // every lane adds 0 except lane 0, and the wave uses lane 0's ticket
         // as a scalar, so the loop exit below is wave-uniform.
@@ -1083,7 +1094,7 @@ __global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
     int* wchunks = s_chunks[threadIdx.x >> 6];
     for (;;) {
         const TraceArgs A = base();
-        double* slot = A.pool + wave * (size_t)A.cap * 64 * 8;
+        double* slot = A.pool + wave * (size_t)A.cap * 64 * kPointDoubles;
         const unsigned ticket = atomicAdd(A.queue, lane == 0 ? 1u : 0u);
         const int item = __builtin_amdgcn_readfirstlane((int)ticket);
         if (item >= A.nbatch) break;
@@ -1121,7 +1132,7 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
     const unsigned total = *A.overflow_count;
     const unsigned tid = blockIdx.x * blockDim.x + threadIdx.x;
     const unsigned stride = gridDim.x * blockDim.x;
-    double* path = A.long_pool + (size_t)tid * (size_t)(A.max_steps + 1) * 8;
+    double* path = A.long_pool + (size_t)tid * (size_t)(A.max_steps + 1) * kPointDoubles;
     for (unsigned k = tid; k < total; k += stride) {
         TraceArgs R = A;
         if (A.overflow_inst) {
@@ -1151,7 +1162,7 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         while (st == kRunning) {
             const double h = rk4_step(R.cam.a, R.cam.m, R.eps, y, sn, cs);
             ++n;
-            store_point(path + (size_t)n * 8, y, h);
+            store_point(path + (size_t)n * kPointDoubles, y, h);
             st = stop_test(R, y, h, n, sn);
         }
         const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
@@ -1159,8 +1170,8 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         Coh N;
         unsigned n_exact = 0;
         for (int m = n_end; m >= 0; --m) {
-            double pt[8];
-            load_point(path + (size_t)m * 8, pt);
+            double pt[kPointDoubles];
+            load_point(path + (size_t)m * kPointDoubles, pt);
             if constexpr (kMode == kModeF32)
                 transfer_point_f32(R, pt, m, m == n_end, xs, N);
             else if constexpr (kKappa<kMode>)
@@ -1202,10 +1213,8 @@ __global__ void bessel_table_nodes(double* vals) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= kBesPanels * kBesCoef) return;
     const int p = idx / kBesCoef, k = idx % kBesCoef;
-    const double width = (kBesT1 - kBesT0) / kBesPanels;
-    const double mid = kBesT0 + (p + 0.5) * width;
     const double z = cos(kPi * (k + 0.5) / kBesCoef);
-    const double x = exp(mid + 0.5 * width * z);
+    const double x = bessel_panel_x(p, z);
     const double k0 = scaled_bessel_k(0.0, x), k1 = scaled_bessel_k(1.0, x), k2 = scaled_bessel_k(2.0, x);
     vals[idx * 2 + 0] = k0 / k2;
     vals[idx * 2 + 1] = k1 / k2;
