@@ -208,24 +208,52 @@ KRT_HD void dmetric_times(const MetricD& d, const double K[4], double o[4]) {
 
 // Geodesic acceleration dK^mu/dlam = -Gamma^mu_ab K^a K^b, written as
 // -g^{mu nu} [K^r (D_r K)_nu + K^h (D_h K)_nu - 1/2 delta_nu^{r,h} K.D K]
-// (only r and theta derivatives are non-zero).
+// (only r and theta derivatives are non-zero), with the Kerr-Schild
+// derivatives factored: d_r g_tt = d_r g_tr = d_r g_rr = f_r and
+// d_r g_tp = d_r g_rp = -a s^2 f_r, so with P = K^t + K^r - a s^2 K^p,
+//   (D_r K)_t = (D_r K)_r = f_r P,  (D_r K)_h = 2 r K^h,
+//   (D_r K)_p = -a s^2 f_r P + 2 r s^2 K^p,  K.D_r K = f_r P^2 + 2 r (K^h^2 + s^2 K^p^2);
+// d_h g_tt = d_h g_tr = d_h g_rr = f_h and d_h g_rp = d_h g_tp - a (s^2)_h, so
+// (D_h K)_r = (D_h K)_t - a (s^2)_h K^p.
 KRT_HD void geodesic_acc_sc(double a, double m, double r, double sn, double cs, const double K[4],
                             double acc[4]) {
-    Metric g;
-    MetricD dr, dh;
-    metric_eval_d_sc(a, m, r, sn, cs, g, dr, dh);
-    double vr[4], vh[4];
-    dmetric_times(dr, K, vr);
-    dmetric_times(dh, K, vh);
-    const double Qr = K[0] * vr[0] + K[1] * vr[1] + K[2] * vr[2] + K[3] * vr[3];
-    const double Qh = K[0] * vh[0] + K[1] * vh[1] + K[2] * vh[2] + K[3] * vh[3];
-    double w[4];
-    for (int k = 0; k < 4; ++k) w[k] = K[1] * vr[k] + K[2] * vh[k];
-    w[1] -= 0.5 * Qr;
-    w[2] -= 0.5 * Qh;
-    double up[4];
-    raise(g, w, up);
-    for (int k = 0; k < 4; ++k) acc[k] = -up[k];
+    const double s2 = sn * sn, c2 = cs * cs, sc = sn * cs, a2 = a * a;
+    const double Sig = r * r + a2 * c2;
+    const double iS = rcp_fast(Sig);
+    const double f = 2.0 * m * r * iS;
+    const double opf = 1.0 + f;
+    // derivatives
+    const double f_r = 2.0 * m * (a2 * c2 - r * r) * iS * iS;
+    const double Sig_h = -2.0 * a2 * sc;
+    const double f_h = -f * Sig_h * iS;
+    const double s2_h = 2.0 * sc;
+    const double gtp_h = -a * (f_h * s2 + f * s2_h);
+    const double grp_h = gtp_h - a * s2_h;
+    const double gpp_h = s2_h * (Sig + a2 * s2 * opf) + s2 * (Sig_h + a2 * (s2_h * opf + s2 * f_h));
+    const double Kt = K[0], Kr = K[1], Kh = K[2], Kp = K[3];
+    const double Ktr = Kt + Kr;
+    // D_r K and D_h K
+    const double as2 = a * s2;
+    const double P = Ktr - as2 * Kp;
+    const double vr0 = f_r * P;
+    const double vr2 = 2.0 * r * Kh;
+    const double vr3 = 2.0 * r * s2 * Kp - as2 * vr0;
+    const double vh0 = f_h * Ktr + gtp_h * Kp;
+    const double vh1 = vh0 - a * s2_h * Kp;
+    const double vh2 = Sig_h * Kh;
+    const double vh3 = gtp_h * Kt + grp_h * Kr + gpp_h * Kp;
+    const double Qr = vr0 * P + 2.0 * r * (Kh * Kh + s2 * Kp * Kp);
+    const double Qh = Kt * vh0 + Kr * vh1 + Kh * vh2 + Kp * vh3;
+    const double w0 = Kr * vr0 + Kh * vh0;
+    const double w1 = Kr * vr0 + Kh * vh1 - 0.5 * Qr;
+    const double w2 = Kr * vr2 + Kh * vh2 - 0.5 * Qh;
+    const double w3 = Kr * vr3 + Kh * vh3;
+    // -g^{mu nu} w_nu: g^tt = -(1 + f), g^tr = f, g^rr = Delta / Sigma,
+    // g^rp = a / Sigma, g^hh = 1 / Sigma, g^pp = 1 / (Sigma s^2)
+    acc[0] = opf * w0 - f * w1;
+    acc[1] = -(f * w0 + ((r * r - 2.0 * m * r + a2) * w1 + a * w3) * iS);
+    acc[2] = -w2 * iS;
+    acc[3] = -(a * w1 + w3 * rcp_fast(s2)) * iS;
 }
 
 KRT_HD void geodesic_acc(double a, double m, double r, double th, const double K[4],

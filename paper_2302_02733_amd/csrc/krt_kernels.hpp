@@ -169,7 +169,7 @@ KRT_HD double rk4_step(double a, double m, double eps, double y[7], double& sn, 
     geo_rhs_sc(a, m, yt, s2, c2, k);
 #pragma unroll
     for (int i = 0; i < 7; ++i) y[i] += h / 6.0 * (ks[i] + k[i]);
-    sincos(y[1], &sn, &cs);
+    sincos_polar(y[1], sn, cs);
     return h;
 }
 
@@ -851,7 +851,7 @@ __device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i,
         y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
     }
     double sn, cs;
-    sincos(y[1], &sn, &cs);
+    sincos_polar(y[1], sn, cs);
     if (kStore && valid) store_point(slot + (size_t)lane * kPointDoubles, y, 0.0);
 
     st = valid ? kRunning : kEscaped;
@@ -1156,7 +1156,7 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         }
         store_point(path, y, 0.0);
         double sn, cs;
-        sincos(y[1], &sn, &cs);
+        sincos_polar(y[1], sn, cs);
         uint8_t st = kRunning;
         int n = 0;
         while (st == kRunning) {
