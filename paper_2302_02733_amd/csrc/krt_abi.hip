@@ -189,6 +189,9 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
         A.snap.dx2 = d.dx2;
         A.snap.x3s = d.x3_start;
         A.snap.dx3 = d.dx3;
+        A.snap.idx1 = 1.0 / d.dx1;   // dx > 0 (checked)
+        A.snap.idx2 = 1.0 / d.dx2;
+        A.snap.idx3 = 1.0 / d.dx3;
         A.snap.h = d.hslope;
         A.snap.gam = d.gamma_ad;
         A.snap.rho_unit = L > 0.0 ? d.M_unit_g / (L * L * L) : 0.0;

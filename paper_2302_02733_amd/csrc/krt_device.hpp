@@ -91,6 +91,64 @@ KRT_HD void sincos_polar(double th, double& s, double& c) {
     c = q == 0 ? pc : (q == 1 ? -st : -pc);
 }
 
+// sin and cos of 2 pi x for any x: reduced to t = 2 pi (x - k/4) in
+// [-pi/4, pi/4] (x - k/4 is exact), the quadrant k mod 4 picking the signs.
+KRT_HD void sincos_2pi(double x, double& s, double& c) {
+    const double k = rint(4.0 * x);
+    const double t = 6.283185307179586 * (x - 0.25 * k);
+    const double t2 = t * t;
+    double ps = kInvFactSin[8], pc = kInvFactCos[8];
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        ps = fma(ps, t2, kInvFactSin[j]);
+        pc = fma(pc, t2, kInvFactCos[j]);
+    }
+    const double st = ps * t;
+    const int q = (int)k & 3;
+    s = q == 0 ? st : (q == 1 ? pc : (q == 2 ? -st : -pc));
+    c = q == 0 ? pc : (q == 1 ? -st : (q == 2 ? -pc : st));
+}
+
+// Natural logarithm of a positive normal x: x = m 2^e with m in [sqrt(1/2),
+// sqrt(2)), ln m = 2 atanh(u) = 2 (u + u^3/3 + ... + u^21/21), u = (m - 1)/(m + 1)
+// (|u| <= 0.172, truncation below 1e-19), plus e ln 2 in two parts.
+KRT_HD double log_pos(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int hi = __double2hiint(x);
+    int e = ((hi >> 20) & 0x7ff) - 1023;
+    int mhi = (hi & 0x000fffff) | 0x3ff00000;
+    if (mhi > 0x3ff6a09e) {   // m > sqrt(2): halve it
+        mhi -= 0x00100000;
+        ++e;
+    }
+    const double m = __hiloint2double(mhi, __double2loint(x));
+#else
+    int e;
+    double m = 2.0 * frexp(x, &e);
+    e -= 1;
+    if (m > 1.4142135623730951) {
+        m *= 0.5;
+        ++e;
+    }
+#endif
+    const double u = (m - 1.0) * rcp_fast(m + 1.0), u2 = u * u;
+    double p = 1.0 / 21.0;
+#pragma unroll
+    for (int k = 19; k >= 1; k -= 2) p = fma(p, u2, 1.0 / k);
+    const double lm = 2.0 * u * p;
+    return fma((double)e, 1.9082149292705877e-10, lm) + (double)e * 0.6931471803691238;
+}
+
+// expm1 for the small arguments of the Planck factor and of the optical
+// depth per step: the Taylor series through x^7 for |x| < 1/64 (relative
+// truncation below 3e-17), else the library expm1.
+KRT_HD double expm1_small(double x) {
+    if (fabs(x) < 0.015625)
+        return x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0 +
+                                                                       x * (1.0 / 720.0 + x * 1.0 / 5040.0))))));
+    return expm1(x);
+}
+
 // ---------------------------------------------------------------------------
 // Kerr-Schild metric at (r, theta): the seven non-zero covariant components,
 // their r and theta derivatives, and the six non-zero inverse components.
@@ -462,6 +520,7 @@ struct SnapDesc {
     const float* prims_f;      // FP32 primitives (same layout)
     int n1, n2, n3;
     double x1s, dx1, x2s, dx2, x3s, dx3;
+    double idx1, idx2, idx3;   // 1 / dx, formed on the host
     double h, gam;
     double rho_unit, B_unit;   // M_unit / L^3 and c sqrt(4 pi rho_unit)
     double Rhigh, Rlow, sigma_cut, rmax;
@@ -472,7 +531,7 @@ struct SnapDesc {
 KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, double P[8]) {
     int i0[3], i1[3];
     double d[3];
-    const double X0 = (x1 - s.x1s) / s.dx1 - 0.5, X1 = (x2 - s.x2s) / s.dx2 - 0.5;
+    const double X0 = (x1 - s.x1s) * s.idx1 - 0.5, X1 = (x2 - s.x2s) * s.idx2 - 0.5;
     const double Xv[2] = {X0, X1};
     const int nn[2] = {s.n1, s.n2};
     for (int k = 0; k < 2; ++k) {
@@ -486,7 +545,7 @@ KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, 
         d[k] = t;
     }
     {
-        const double X2 = (x3 - s.x3s) / s.dx3 - 0.5;
+        const double X2 = (x3 - s.x3s) * s.idx3 - 0.5;
         const double f = floor(X2);
         long i = (long)f;
         const long n = s.n3;
@@ -528,14 +587,14 @@ KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, 
 // poisons the ray: its pixel is written as NONFINITE).
 KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, double th, double ph,
                            const Metric& g, Plasma& p) {
-    const double x1 = log(r);
+    const double x1 = log_pos(r);
     double x2 = th * (1.0 / kPi);
     const double hh = 0.5 * (1.0 - s.h);
     // Newton from theta/pi: quadratic convergence, at most 8 steps, stopping
     // once a step no longer moves x2 beyond round-off
     for (int it = 0; it < 8; ++it) {
         double sn, cs;
-        sincos(2.0 * kPi * x2, &sn, &cs);
+        sincos_2pi(x2, sn, cs);
         const double dx = (kPi * x2 + hh * sn - th) * rcp_fast(kPi * (1.0 + (1.0 - s.h) * cs));
         x2 -= dx;
         if (fabs(dx) < 1e-15) break;
@@ -544,14 +603,16 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     snapshot_interp(s, x1, x2, ph, P);
     if (!is_finite(P[0] + P[1] + P[2] + P[3] + P[4] + P[5] + P[6] + P[7])) return 2;
     const double rho = P[0], uu = P[1];
-    const double J2 = kPi * (1.0 + (1.0 - s.h) * cos(2.0 * kPi * x2));
+    double s2x, c2x;
+    sincos_2pi(x2, s2x, c2x);
+    const double J2 = kPi * (1.0 + (1.0 - s.h) * c2x);
     const double U[4] = {0.0, P[2] * r, P[3] * J2, P[4]};
     const double Bv[4] = {0.0, P[5] * r, P[6] * J2, P[7]};
     // g_ij U^i U^j (spatial part)
     const double q = g.rr * U[1] * U[1] + 2.0 * g.rp * U[1] * U[3] + g.hh * U[2] * U[2] + g.pp * U[3] * U[3];
     const double gamma = sqrt(1.0 + q);
     const double lapse = rsqrt_fast(-g.Itt);
-    p.u[0] = gamma / lapse;
+    p.u[0] = gamma * (-g.Itt * lapse);   // gamma / lapse
     p.u[1] = U[1] - gamma * lapse * g.Itr;
     p.u[2] = U[2];
     p.u[3] = U[3];
@@ -569,13 +630,15 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     p.ne = rho * s.rho_unit / (kMP + kME);
     double thetae = 0.0;
     if (rho > 0.0 && uu > 0.0) {
-        const double ib = 0.5 * bsq / ((s.gam - 1.0) * uu);
+        // 1/beta = (b.b/2) / ((gamma_ad - 1) u); T_i/T_e = (R_high + R_low / beta^2) / (1 + 1/beta^2)
+        const double ib = 0.5 * bsq * rcp_fast((s.gam - 1.0) * uu);
         const double ib2 = ib * ib;
-        const double trat = (s.Rhigh + s.Rlow * ib2) / (1.0 + ib2);
-        thetae = (kMP / kME) * (s.gam - 1.0) * (uu / rho) / (1.0 + trat);
+        const double iden = rcp_fast(1.0 + ib2);
+        const double trat = (s.Rhigh + s.Rlow * ib2) * iden;
+        thetae = (kMP / kME) * (s.gam - 1.0) * uu * rcp_fast(rho * (1.0 + trat));
     }
     p.thetae = thetae;
-    if (!(rho > 0.0) || bsq / rho > s.sigma_cut || r > s.rmax) p.ne = 0.0;
+    if (!(rho > 0.0) || bsq > s.sigma_cut * rho || r > s.rmax) p.ne = 0.0;
     (void)a;
     (void)m;
     return 1;
@@ -736,7 +799,7 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     out[0] = jI;
     out[1] = jQ;
     out[2] = jV;
-    const double em1 = expm1(kHnuOverTheta * nu * iTh);
+    const double em1 = expm1_small(kHnuOverTheta * nu * iTh);
     const double seq = kSrcFac * rcp_fast(em1);
     const double Bnu = seq * nu * nu * nu;
     if (jI > 0.0 && Bnu > 0.0) {
@@ -805,7 +868,7 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         // series in X and Z = -Y: c2 = sum_k h_k/(2k)!, c3 = sum_k h_k/(2k+1)!,
         // c0 = 1 - X Z sum_{k>=1} h_k/(2k+2)!, c1 = 1 - X Z sum_{k>=1} h_k/(2k+3)!,
         // h_k = sum_{j<k} X^j Z^(k-1-j) (h_1 = 1, h_{k+1} = X h_k + Z^k).
-        const double em1 = expm1(-tau);
+        const double em1 = expm1_small(-tau);
         const double et = 1.0 + em1;
         const double Z = -Y;
         double h = 1.0, zk = 1.0;
@@ -848,7 +911,7 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
         // sin^2(y/2) = sin^2 y / (2 (1 + cos y)) (cos y > 0) or (1 - cos y) / 2
         const double qh = 0.5 * (u - v);
         const double s2h = (cy > 0.0) ? 0.5 * sy * sy * rcp_fast(1.0 + cy) : 0.5 * (1.0 - cy);
-        omd0 = -expm1(-tau) + 2.0 * (X * et * s2h - Y * qh * qh) * iXY;
+        omd0 = -expm1_small(-tau) + 2.0 * (X * et * s2h - Y * qh * qh) * iXY;
     }
     double D[4] = {S[0] - Seq, S[1], S[2], S[3]};
     double T[4], U[4];

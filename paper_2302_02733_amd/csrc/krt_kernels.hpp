@@ -558,7 +558,7 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles
     int pk = 0;
     if (A.model == kModelSnapshot) {
         const SnapDesc& q = A.snap;
-        double X2 = (pt[2] - q.x3s) / q.dx3 - 0.5;
+        double X2 = (pt[2] - q.x3s) * q.idx3 - 0.5;
         X2 -= q.n3 * floor(X2 / q.n3);
         // no plasma beyond the emission radius (n_e = 0: every coefficient zero)
         if (pt[0] <= q.rmax)

@@ -51,12 +51,8 @@ def _gpu_image(ctx, w, nsteps=True):
 
 
 def _compare_images(S, So, st=None, sto=None, ns=None, nso=None):
-    """The image bar.  Step counts: a ray whose state passes within round-off
-    of a stop threshold can take one step more or fewer than the oracle's
-    (the two sum the same RK4 stages in different orders, ~1e-13 apart), and
-    rays that orbit near the photon ring amplify such differences; up to 0.1%
-    of the rays may therefore differ by at most two steps.  Everything else,
-    and the status of every ray whose step count agrees, must be equal."""
+    """The image bar: p99 of |dS|/I_max and the total fluxes (above), step
+    counts and ray status identical to the oracle's for every ray."""
     imax = So[0].max()
     assert imax > 0
     for s in range(4):
@@ -71,11 +67,9 @@ def _compare_images(S, So, st=None, sto=None, ns=None, nso=None):
     if ns is not None:
         same = ns == nso
         _log(f"step counts differing from the oracle: {int((~same).sum())} of {same.size}")
-        assert np.mean(same) >= 0.999
-        assert np.abs(ns - nso).max() <= 2
+        assert np.array_equal(ns, nso)
     if st is not None:
-        assert np.array_equal(st[same], sto[same])
-        assert np.mean(st == sto) >= 0.999
+        assert np.array_equal(st, sto)
     # realizability (P12) of the GPU image
     I, Q, U, V = S
     assert np.all(I * I * (1 + P_EXCESS_TOL) >= Q * Q + U * U + V * V)
