@@ -56,6 +56,7 @@ class Model(ctypes.Structure):
         ("slab_bdir", ctypes.c_double * 3), ("slab_jextra", ctypes.c_double * 3),
         ("slab_coef", ctypes.c_double * 8),
         ("electrons", ctypes.c_int32), ("kappa", ctypes.c_double),
+        ("update_empty", ctypes.c_int32),
     ]
 
 
@@ -159,6 +160,7 @@ def make_model(d):
             arr[k] = float(v[k])
     m.electrons = int(d.get("electrons", 0))
     m.kappa = float(d.get("kappa", 0.0))
+    m.update_empty = int(d.get("update_empty", 0))
     return m
 
 

@@ -75,6 +75,10 @@ typedef struct {
      * `kappa` with width Theta_e (the nonthermal module) */
     int32_t electrons;
     double kappa;
+    /* 1: the radiative update also at points where every coefficient is zero
+     * (projection on the fluid legs and rebuild, as the update is first
+     * stated); 0 (the reading both sides use): such points leave N as it is */
+    int32_t update_empty;
 } or_model;
 
 /* Gridded snapshot description (modified Kerr-Schild grid). */

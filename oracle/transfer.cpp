@@ -279,7 +279,7 @@ static void radiative_update(const or_camera* cam, double L_cm, const or_model* 
      * projection sees; the point leaves N as it is. */
     bool zero = true;
     for (int k = 0; k < 8; ++k) zero = zero && coef[k] == 0.0;
-    if (zero) return;
+    if (zero && !model->update_empty) return;
     FluidFrame F;
     fluid_frame(g, p.u, K, p.b, &F);
     double S[4], S2[4];
