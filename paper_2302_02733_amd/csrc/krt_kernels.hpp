@@ -918,7 +918,7 @@ __device__ __forceinline__ void stage_table(TraceArgs& A, double* s_btab, float*
 // modes run one.
 // ---------------------------------------------------------------------------
 template <int kMode>
-__global__ __launch_bounds__(256, kKappa<kMode> ? 1 : (kMode == kModeF32 ? 3 : 2)) void trace_waves(TraceArgs A) {
+__global__ __launch_bounds__(256, kMode == kModeKapExact ? 1 : (kMode == kModeF32 ? 3 : 2)) void trace_waves(TraceArgs A) {
     constexpr bool kGeoOnly = kMode == kModeGeo;
     constexpr int kTab = kBesPanels * 2 * kBesCoef;
     __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];

@@ -372,6 +372,8 @@ struct MlpPacked {
     float mu[8], sd[8];
     float poly[8][kPolyTerms];
 };
+// The packed network as read from LDS.
+typedef __attribute__((address_space(3))) const MlpPacked LdsMlp;
 
 // Hidden unit fed to B-operand position (K step ks, lane half hf, element e):
 // the unit held by that lane's accumulator of the previous layer, register
@@ -433,14 +435,15 @@ __device__ __forceinline__ void split8(const float x[8], bf16x8& hi, bf16x8& lo)
 
 // Bias in accumulator layout: register v of M tile mt holds row
 // 32 mt + 8 (v / 4) + 4 hf + v % 4.
-__device__ __forceinline__ void bias_init(const float* b, int mt, int hf, f32x16& acc) {
+template <class P>
+__device__ __forceinline__ void bias_init(P b, int mt, int hf, f32x16& acc) {
     for (int v = 0; v < 16; ++v) acc[v] = b[32 * mt + 8 * (v >> 2) + 4 * hf + (v & 3)];
 }
 
 // One 32-ray tile: x = this lane's feature row for the tile (zeros in the
 // upper half-wave); returns in z[0..3] the outputs 4 hf .. 4 hf + 3 of ray
 // (lane & 31) of the tile.  Must be called by all 64 lanes together.
-__device__ __forceinline__ void mlp_tile(const MlpPacked* __restrict__ W, const float x[8], float z[4]) {
+__device__ __forceinline__ void mlp_tile(LdsMlp* __restrict__ W, const float x[8], float z[4]) {
     const int lane = threadIdx.x & 63, hf = lane >> 5;
     f32x16 acc[2];
     bf16x8 bh[4], bl[4];
@@ -461,7 +464,7 @@ __device__ __forceinline__ void mlp_tile(const MlpPacked* __restrict__ W, const 
             split8(a, bh[ks], bl[ks]);
         }
         const int fw = L ? kFragW3 : kFragW2;
-        const float* b = L ? W->b3 : W->b2;
+        const auto b = L ? W->b3 : W->b2;
         for (int mt = 0; mt < 2; ++mt) {
             bias_init(b, mt, hf, acc[mt]);
             for (int ks = 0; ks < 4; ++ks) {
@@ -506,7 +509,12 @@ __device__ __forceinline__ void mlp_wave(const MlpPacked* __restrict__ W, const 
             x[k] = hf == 0 ? v : 0.0f;
         }
         for (int k = 4; k < 8; ++k) x[k] = 0.0f;
-        mlp_tile(W, x, zt[nt]);
+        // the weights are read again for each tile: an address the compiler
+        // cannot see through keeps it from holding all 22 fragments (88
+        // registers) from the first tile into the second
+        LdsMlp* Wt = (LdsMlp*)W;
+        asm volatile("" : "+v"(Wt));
+        mlp_tile(Wt, x, zt[nt]);
     }
     // ray R = lane sits in tile hf at column lane & 31: this lane holds its
     // outputs 4 hf .. 4 hf + 3, the partner lane (lane ^ 32) the other four,
