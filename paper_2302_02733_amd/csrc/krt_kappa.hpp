@@ -22,6 +22,7 @@
 // depend on (kappa, w, X) only.
 #pragma once
 
+#include <type_traits>
 #include "krt_device.hpp"
 
 namespace krt {
@@ -263,17 +264,24 @@ KRT_HD void kappa_physical(const double I[8], double ne, double B, double nu, do
 // step, below 1e-20 by n = 21).  Relative error a few ulp for every tau >= 0.
 constexpr double kInvFact81 = 1.724992688482352e-121;   // 1/81!
 
-KRT_HD void phi1_taylor(double z, double t[22]) {
+// Storage of a lane's 22 coefficients in LDS (entry n at p[64 n]: the
+// lanes of a wave side by side), for kernels without registers to hold them.
+struct LdsLaneTab {
+    volatile __attribute__((address_space(3))) double* p;
+    __device__ __forceinline__ volatile __attribute__((address_space(3))) double& operator[](int n) const {
+        return p[n << 6];
+    }
+};
+
+// t: double[22] or LdsLaneTab.
+template <class Tab>
+KRT_HD void phi1_taylor(double z, Tab& t) {
     const double tau = -z;
     const double ez = exp(z);
     t[0] = (tau > 0.0) ? expm1(z) / z : 1.0;
-    int m = 0;
-    if (tau >= 1.0) {
-        m = tau >= 21.0 ? 21 : (int)tau;
-        const double it = 1.0 / tau;
-        for (int n = 1; n <= m; ++n) t[n] = (t[n - 1] - ez * kInvFact[n]) * it;
-    }
-    if (m < 21) {
+    if constexpr (std::is_array<Tab>::value) {
+        // a register table: fixed indices only.  Downward for every tau, the
+        // values at n <= tau replaced by the upward ones
         double f = kInvFact81 * 81.0;                      // 1/80!
         double tn = ez * kInvFact81 / (1.0 - tau / 82.0);  // t_80
         for (int n = 80; n >= 22; --n) {
@@ -281,15 +289,48 @@ KRT_HD void phi1_taylor(double z, double t[22]) {
             f *= (double)n;
         }
         t[21] = tn;
-        for (int n = 21; n >= m + 2; --n) t[n - 1] = ez * kInvFact[n] + tau * t[n];
+#pragma unroll
+        for (int n = 21; n >= 2; --n) t[n - 1] = ez * kInvFact[n] + tau * t[n];
+        if (tau >= 1.0) {
+            const int m = tau >= 21.0 ? 21 : (int)tau;
+            const double it = 1.0 / tau;
+            double u = t[0];
+#pragma unroll
+            for (int n = 1; n <= 21; ++n) {
+                u = (u - ez * kInvFact[n]) * it;
+                if (n <= m) t[n] = u;
+            }
+        }
+    } else {
+        // a table in memory: each entry computed once
+        int m = 0;
+        if (tau >= 1.0) {
+            m = tau >= 21.0 ? 21 : (int)tau;
+            const double it = 1.0 / tau;
+            for (int n = 1; n <= m; ++n) t[n] = (t[n - 1] - ez * kInvFact[n]) * it;
+        }
+        if (m < 21) {
+            double f = kInvFact81 * 81.0;                      // 1/80!
+            double tn = ez * kInvFact81 / (1.0 - tau / 82.0);  // t_80
+            for (int n = 80; n >= 22; --n) {
+                tn = ez * f + tau * tn;                        // t_(n-1)
+                f *= (double)n;
+            }
+            t[21] = tn;
+            for (int n = 21; n >= m + 2; --n) {
+                tn = ez * kInvFact[n] + tau * tn;
+                t[n - 1] = tn;
+            }
+        }
     }
 }
 
 // phi1 at a real z <= 0.
 KRT_HD double phi1_real(double z) { return (z == 0.0) ? 1.0 : expm1(z) / z; }
 
+template <class Tab>
 KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double AQ, double AV, double RQ,
-                            double RV, double w, double S[4]) {
+                            double RV, double w, double S[4], Tab& t) {
     const double tau = AI * w;
     const double a2 = (AQ * AQ + AV * AV) * w * w;
     const double r2 = (RQ * RQ + RV * RV) * w * w;
@@ -306,7 +347,6 @@ KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double A
     }
     const double XY = X + Y;
     const double Z = -Y;
-    double t[22];
     phi1_taylor(-tau, t);
     const double em1 = expm1(-tau);
     const double et = 1.0 + em1;
@@ -405,6 +445,12 @@ KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double A
     for (int k = 0; k < 4; ++k) T[k] = d1 * S[k] + b1 * J[k] + U[k];
     gen_apply(gQ, gV, hQ, hV, T, U);
     for (int k = 0; k < 4; ++k) S[k] = d0 * S[k] + b0 * J[k] + U[k];
+}
+
+KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double AQ, double AV, double RQ,
+                            double RV, double w, double S[4]) {
+    double t[22];
+    mueller_general(JI, JQ, JV, AI, AQ, AV, RQ, RV, w, S, t);
 }
 
 }  // namespace krt

@@ -83,6 +83,7 @@ struct TraceArgs {
     double kappa;
     const double* syntab;       // synchrotron-function table
     const MlpPacked* mlp;       // packed surrogate
+    double* phi_lds;            // per-lane phi1 tables in LDS (set inside the kernel)
     // measurement probe (plain mode): queue item t is listed pixel probe_pix[t],
     // traced by all 64 lanes of the wave; Stokes written as [4][probe_np]
     const int32_t* probe_pix;
@@ -258,12 +259,14 @@ struct LdsTables {
     const double* btab;
     const float* btab_f;
     const MlpPacked* mlp;
+    double* phi;
 };
 
 KRT_HD void use_lds(TraceArgs& L, const LdsTables& T) {
     if (T.btab) L.btab = T.btab;
     if (T.btab_f) L.btab_f = T.btab_f;
     if (T.mlp) L.mlp = T.mlp;
+    L.phi_lds = T.phi;
 }
 
 // Parameters of the plain tracer: its arguments (args: the kernel-argument
@@ -423,6 +426,7 @@ KRT_HD int kappa_point(const TraceArgs& A, const double pt[kPointDoubles], Plasm
 // integrals I_in when use_in, else from the exact integrator (counted in
 // n_exact); the update is the general constant-coefficient one.  pre: the
 // plasma at the point when already evaluated, pre_kind its plasma_at result.
+template <bool kPhiLds = false>
 KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[kPointDoubles], int n, bool first, XferState& st,
                                  Coh& N, const double* I_in, bool use_in, unsigned& n_exact,
                                  const Plasma* pre = nullptr, int pre_kind = 0) {
@@ -486,8 +490,16 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[kPointDoubl
                 fluid_legs(g, p.u, K, p.b, bb, Ku, e1, l1, e2, l2);
                 double S[4];
                 coh_project(N, l1, l2, S);
-                mueller_general(fj * c[0], fj * c[1], fj * c[2], fa * c[3], fa * c[4], fa * c[5], fa * c[6],
-                                fa * c[7], 0.5 * (Dn + Dnext), S);
+                if constexpr (kPhiLds) {
+                    // this lane's slice of its wave's LDS block [22][64]
+                    LdsLaneTab t{(__attribute__((address_space(3))) double*)A.phi_lds +
+                                 (threadIdx.x >> 6) * (22 * 64) + (threadIdx.x & 63)};
+                    mueller_general(fj * c[0], fj * c[1], fj * c[2], fa * c[3], fa * c[4], fa * c[5], fa * c[6],
+                                    fa * c[7], 0.5 * (Dn + Dnext), S, t);
+                } else {
+                    mueller_general(fj * c[0], fj * c[1], fj * c[2], fa * c[3], fa * c[4], fa * c[5], fa * c[6],
+                                    fa * c[7], 0.5 * (Dn + Dnext), S);
+                }
                 coh_rebuild(N, S, e1, e2);
             }
         }
@@ -788,7 +800,7 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
                 load_point(point_addr(A, slot, wchunks, m, lane), pt);
                 n_mlp += want ? 1u : 0u;
                 n_exact += fall ? 1u : 0u;
-                transfer_point_kappa(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, pk);
+                transfer_point_kappa<true>(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, pk);
             }
         } else {
             double pt[kPointDoubles];
@@ -924,6 +936,9 @@ __global__ __launch_bounds__(256, kMode == kModeKapExact ? 1 : (kMode == kModeF3
     __shared__ double s_btab[kMode == kModeF64 ? kTab : 1];
     __shared__ float s_btab_f[kMode == kModeF32 ? kTab : 1];
     __shared__ int4 s_mlp[kMode == kModeKapMlp ? sizeof(MlpPacked) / 16 : 1];
+    // the surrogate kernel (two waves per SIMD) keeps the general update's
+    // Taylor table in LDS rather than in registers
+    __shared__ double s_phi[kMode == kModeKapMlp ? 4 * 22 * 64 : 1];
     stage_table<kMode>(A, s_btab, s_btab_f);
     if constexpr (kMode == kModeKapMlp) {
         const int4* src = reinterpret_cast<const int4*>(A.mlp);
@@ -933,7 +948,8 @@ __global__ __launch_bounds__(256, kMode == kModeKapExact ? 1 : (kMode == kModeF3
     }
     const PlainSource src{(const TraceArgs*)__builtin_amdgcn_kernarg_segment_ptr(),
                           {kMode == kModeF64 ? s_btab : nullptr, kMode == kModeF32 ? s_btab_f : nullptr,
-                           kMode == kModeKapMlp ? reinterpret_cast<const MlpPacked*>(s_mlp) : nullptr}};
+                           kMode == kModeKapMlp ? reinterpret_cast<const MlpPacked*>(s_mlp) : nullptr,
+                           kMode == kModeKapMlp ? s_phi : nullptr}};
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: read it from the first lane so that the
     // slice address lives in scalar registers

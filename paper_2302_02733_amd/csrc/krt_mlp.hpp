@@ -424,12 +424,22 @@ __device__ __forceinline__ float silu_fast(float z) {
     return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
 
-// hi + lo bfloat16 split of 8 floats.
+// hi + lo bfloat16 split of 8 floats, two at a time: hi = x rounded to the
+// nearest bfloat16 (ties to even: one hardware conversion per pair), lo = the
+// remainder x - hi (exact in FP32) rounded the same way.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void split8(const float x[8], bf16x8& hi, bf16x8& lo) {
-    for (int e = 0; e < 8; ++e) {
-        const float h = bf16_round(x[e]);
-        hi[e] = (__bf16)h;
-        lo[e] = (__bf16)bf16_round(x[e] - h);
+    for (int q = 0; q < 4; ++q) {
+        const f32x2 v = {x[2 * q], x[2 * q + 1]};
+        const bf16x2 h = __builtin_convertvector(v, bf16x2);
+        const uint32_t u = __builtin_bit_cast(uint32_t, h);
+        const f32x2 r = {v.x - __builtin_bit_cast(float, u << 16), v.y - __builtin_bit_cast(float, u & 0xFFFF0000u)};
+        const bf16x2 l = __builtin_convertvector(r, bf16x2);
+        hi[2 * q] = h.x;
+        hi[2 * q + 1] = h.y;
+        lo[2 * q] = l.x;
+        lo[2 * q + 1] = l.y;
     }
 }
 
