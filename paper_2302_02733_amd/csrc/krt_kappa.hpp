@@ -264,6 +264,25 @@ KRT_HD void kappa_physical(const double I[8], double ne, double B, double nu, do
 // step, below 1e-20 by n = 21).  Relative error a few ulp for every tau >= 0.
 constexpr double kInvFact81 = 1.724992688482352e-121;   // 1/81!
 
+// e^-z t_21 by the downward recurrence in scaled form, s_(n-1) = 1/n! + tau s_n,
+// from s_n0 = 1 / ((n0+1)! (1 - tau/(n0+2))).  The start's relative error,
+// about (tau/n0)^2, is damped by tau/n per step: n0 = 32 for tau < 1 leaves
+// below 1e-19 at n = 21, n0 = 80 covers tau < 21 (where the downward values
+// are used).
+constexpr double kInvFact33 = 1.151633562077195e-37;   // 1/33!
+KRT_HD double phi1_tail_scaled(double tau) {
+    const bool low = tau < 1.0;
+    const int n0 = low ? 32 : 80;
+    const double inv = low ? kInvFact33 : kInvFact81;   // 1/(n0+1)!
+    double f = inv * (double)(n0 + 1);                  // 1/n0!
+    double s = inv / (1.0 - tau / (double)(n0 + 2));
+    for (int n = n0; n >= 22; --n) {
+        s = f + tau * s;                                 // s_(n-1)
+        f *= (double)n;
+    }
+    return s;
+}
+
 // Storage of a lane's 22 coefficients in LDS (entry n at p[64 n]: the
 // lanes of a wave side by side), for kernels without registers to hold them.
 struct LdsLaneTab {
@@ -282,13 +301,7 @@ KRT_HD void phi1_taylor(double z, Tab& t) {
     if constexpr (std::is_array<Tab>::value) {
         // a register table: fixed indices only.  Downward for every tau, the
         // values at n <= tau replaced by the upward ones
-        double f = kInvFact81 * 81.0;                      // 1/80!
-        double tn = ez * kInvFact81 / (1.0 - tau / 82.0);  // t_80
-        for (int n = 80; n >= 22; --n) {
-            tn = ez * f + tau * tn;                        // t_(n-1)
-            f *= (double)n;
-        }
-        t[21] = tn;
+        t[21] = ez * phi1_tail_scaled(tau);
 #pragma unroll
         for (int n = 21; n >= 2; --n) t[n - 1] = ez * kInvFact[n] + tau * t[n];
         if (tau >= 1.0) {
@@ -310,12 +323,7 @@ KRT_HD void phi1_taylor(double z, Tab& t) {
             for (int n = 1; n <= m; ++n) t[n] = (t[n - 1] - ez * kInvFact[n]) * it;
         }
         if (m < 21) {
-            double f = kInvFact81 * 81.0;                      // 1/80!
-            double tn = ez * kInvFact81 / (1.0 - tau / 82.0);  // t_80
-            for (int n = 80; n >= 22; --n) {
-                tn = ez * f + tau * tn;                        // t_(n-1)
-                f *= (double)n;
-            }
+            double tn = ez * phi1_tail_scaled(tau);            // t_21
             t[21] = tn;
             for (int n = 21; n >= m + 2; --n) {
                 tn = ez * kInvFact[n] + tau * tn;

@@ -503,6 +503,15 @@ __device__ __forceinline__ void mlp_tile(LdsMlp* __restrict__ W, const float x[8
     for (int v = 0; v < 4; ++v) z[v] = o[v];
 }
 
+// 10^y for an output of the network (y in FP32): 2^e = 2^k 2^(e - k) with
+// e = y log2 10 formed in FP64, k = rint(e), 2^(e - k) by the hardware's FP32
+// exp2; relative error about 1e-7, as y itself carries.
+__device__ __forceinline__ double exp10_out(float y) {
+    const double e = (double)y * 3.321928094887362;
+    const double k = __builtin_rint(e);
+    return __builtin_ldexp((double)__builtin_amdgcn_exp2f((float)(e - k)), (int)k);
+}
+
 // The network for the 64 lanes of a wave: f = this lane's features; on
 // return out[8] = the eight integrals of this lane (log10 destandardised and
 // exponentiated).  Must be called by all 64 lanes together.
@@ -541,7 +550,7 @@ __device__ __forceinline__ void mlp_wave(const MlpPacked* __restrict__ W, const 
     for (int o = 0; o < 8; ++o) {
         float base = 0.0f;
         for (int j = 0; j < kPolyTerms; ++j) base += W->poly[o][j] * m[j];
-        out[o] = exp10((double)(base + W->mu[o] + W->sd[o] * z[o]));
+        out[o] = exp10_out(base + W->mu[o] + W->sd[o] * z[o]);
     }
 }
 
