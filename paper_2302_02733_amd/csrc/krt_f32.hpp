@@ -36,6 +36,72 @@ struct F32Consts {
     float x1s, idx1, x2s, idx2, hh, gm1, ne_unit, B_unit, Rhigh, Rlow, sigma_cut, rmax, mpme;
 };
 
+// Reciprocal, square root and reciprocal square root on the FP32 units (about
+// 1 ulp): the operators of this mode need no correctly rounded division or
+// square root, whose expansions take 12 and 17 instructions.
+KRT_HD float rcpf_fast(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+KRT_HD float sqrtf_fast(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+KRT_HD float rsqrtf_fast(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
+
+// exp, log and expm1 from the hardware's base-2 exp and log (relative error
+// about |x| 2^-24 plus an ulp, against the library's correctly reduced forms);
+// x^(-1/3) from them with one Newton step.
+KRT_HD float expf_fast(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_exp2f(x * 1.44269504f);
+#else
+    return expf(x);
+#endif
+}
+KRT_HD float logf_fast(float x) {   // x > 0, normal
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x) * 0.693147181f;
+#else
+    return logf(x);
+#endif
+}
+// Taylor series through x^6 for |x| < 1/8 (relative truncation below 1e-9).
+KRT_HD float expm1f_fast(float x) {
+    if (fabsf(x) < 0.125f)
+        return x * (1.0f + x * (0.5f + x * (1.0f / 6.0f + x * (1.0f / 24.0f + x * (1.0f / 120.0f + x * (1.0f / 720.0f))))));
+    return expf_fast(x) - 1.0f;
+}
+KRT_HD float rcbrtf_fast(float x) {   // x > 0, normal
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float y = __builtin_amdgcn_exp2f(-0.333333343f * __builtin_amdgcn_logf(x));
+    return y * (4.0f - x * y * y * y) * 0.333333343f;   // y (4 - x y^3) / 3
+#else
+    return 1.0f / cbrtf(x);
+#endif
+}
+// sin and cos of 2 pi t for t in [-256, 256] (turns), on the hardware units.
+KRT_HD void sincos_turns_f(float t, float& sn, float& cs) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    sn = __builtin_amdgcn_sinf(t);
+    cs = __builtin_amdgcn_cosf(t);
+#else
+    sincosf(6.28318531f * t, &sn, &cs);
+#endif
+}
+
 struct MetricF {
     float s, c, Sig;
     float tt, tr, tp, rr, rp, hh, pp;
@@ -52,7 +118,7 @@ KRT_HD void metric_d_f(float a, float m, float r, float s, float c, MetricF& g, 
                        MetricDF& dh) {
     const float s2 = s * s, sc = s * c, a2 = a * a;
     const float Sig = r * r + a2 * c * c;
-    const float iS = 1.0f / Sig;
+    const float iS = rcpf_fast(Sig);
     const float f = 2.0f * m * r * iS;
     const float opf = 1.0f + f;
     g.s = s;
@@ -70,7 +136,7 @@ KRT_HD void metric_d_f(float a, float m, float r, float s, float c, MetricF& g, 
     g.Irr = (r * r - 2.0f * m * r + a2) * iS;
     g.Irp = a * iS;
     g.Ihh = iS;
-    g.Ipp = iS / s2;
+    g.Ipp = iS * rcpf_fast(s2);
     const float Sig_h = -2.0f * a2 * sc;
     const float f_r = 2.0f * m * (a2 * c * c - r * r) * iS * iS;
     const float f_h = -f * Sig_h * iS;
@@ -160,28 +226,29 @@ struct PlasmaF {
 
 // Analytic ADAF (same model as the FP64 path).
 KRT_HD bool adaf_plasma_f(const F32Consts& C, float r, const MetricF& g, PlasmaF& p) {
-    const float sr = sqrtf(r);
-    p.ne = C.n0 / (r * sr) * expf(-g.c * g.c * C.ih2);
-    p.thetae = C.thr / r;
-    p.B = sqrtf(C.cB2 * p.ne / r);
+    const float sr = sqrtf_fast(r);
+    p.ne = C.n0 * rcpf_fast(r * sr) * expf_fast(-g.c * g.c * C.ih2);
+    const float ir = rcpf_fast(r);
+    p.thetae = C.thr * ir;
+    p.B = sqrtf_fast(C.cB2 * p.ne * ir);
     float Om = 0.0f, norm = 1.0f;
     const bool kepler = (C.m != 0.0f) && (r >= C.risco);
     if (kepler) {
-        Om = 1.0f / (r * sr + C.a);
+        Om = rcpf_fast(r * sr + C.a);
         norm = g.tt + 2.0f * g.tp * Om + g.pp * Om * Om;
     }
     if (!kepler || !(norm < 0.0f)) {
-        Om = -g.tp / g.pp;
+        Om = -g.tp * rcpf_fast(g.pp);
         norm = g.tt + 2.0f * g.tp * Om + g.pp * Om * Om;
     }
     if (!(norm < 0.0f)) return false;
-    const float ut = 1.0f / sqrtf(-norm);
+    const float ut = rsqrtf_fast(-norm);
     p.u[0] = ut;
     p.u[1] = 0.0f;
     p.u[2] = 0.0f;
     p.u[3] = Om * ut;
     const float uph = g.tp * ut + g.pp * p.u[3];
-    const float sc = p.B / sqrtf(g.pp + uph * uph);
+    const float sc = p.B * rsqrtf_fast(g.pp + uph * uph);
     p.b[0] = sc * uph * p.u[0];
     p.b[1] = 0.0f;
     p.b[2] = 0.0f;
@@ -234,18 +301,21 @@ KRT_HD void snapshot_interp_f(const P* prims, int n1, int n2, int n3, float X0, 
 template <class P>
 KRT_HD int snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2, int n3, float r,
                              float th, float X2, const MetricF& g, PlasmaF& p) {
-    const float x1 = logf(r);
+    const float x1 = logf_fast(r);
     const float kPif = 3.14159265f;
     float x2 = th * (1.0f / kPif);
     float cs2 = 1.0f;
     for (int it = 0; it < 8; ++it) {
         float sn;
-        sincosf(2.0f * kPif * x2, &sn, &cs2);
-        const float dx = (kPif * x2 + C.hh * sn - th) / (kPif * (1.0f + 2.0f * C.hh * cs2));
+        sincos_turns_f(x2, sn, cs2);
+        const float dx = (kPif * x2 + C.hh * sn - th) * rcpf_fast(kPif * (1.0f + 2.0f * C.hh * cs2));
         x2 -= dx;
         if (fabsf(dx) < 1e-7f) break;
     }
-    cs2 = cosf(2.0f * kPif * x2);
+    {
+        float sn;
+        sincos_turns_f(x2, sn, cs2);
+    }
     float Pv[8];
     snapshot_interp_f(prims, n1, n2, n3, (x1 - C.x1s) * C.idx1 - 0.5f, (x2 - C.x2s) * C.idx2 - 0.5f,
                       X2, Pv);
@@ -255,32 +325,32 @@ KRT_HD int snapshot_plasma_f(const F32Consts& C, const P* prims, int n1, int n2,
     const float U1 = Pv[2] * r, U2 = Pv[3] * J2, U3 = Pv[4];
     const float B1 = Pv[5] * r, B2 = Pv[6] * J2, B3 = Pv[7];
     const float q = g.rr * U1 * U1 + 2.0f * g.rp * U1 * U3 + g.hh * U2 * U2 + g.pp * U3 * U3;
-    const float gamma = sqrtf(1.0f + q);
-    const float lapse = 1.0f / sqrtf(-g.Itt);
-    p.u[0] = gamma / lapse;
+    const float gamma = sqrtf_fast(1.0f + q);
+    const float lapse = rsqrtf_fast(-g.Itt);
+    p.u[0] = gamma * sqrtf_fast(-g.Itt);   // gamma / lapse
     p.u[1] = U1 - gamma * lapse * g.Itr;
     p.u[2] = U2;
     p.u[3] = U3;
     float ul[4];
     lower_f(g, p.u, ul);
     const float bt = B1 * ul[1] + B2 * ul[2] + B3 * ul[3];
-    const float iut = 1.0f / p.u[0];
+    const float iut = rcpf_fast(p.u[0]);
     p.b[0] = bt;
     p.b[1] = (B1 + bt * p.u[1]) * iut;
     p.b[2] = (B2 + bt * p.u[2]) * iut;
     p.b[3] = (B3 + bt * p.u[3]) * iut;
     const float bsq = dot_f(g, p.b, p.b);
-    p.B = sqrtf(bsq > 0.0f ? bsq : 0.0f) * C.B_unit;
+    p.B = sqrtf_fast(bsq > 0.0f ? bsq : 0.0f) * C.B_unit;
     p.ne = rho * C.ne_unit;
     float thetae = 0.0f;
     if (rho > 0.0f && uu > 0.0f) {
-        const float ib = 0.5f * bsq / (C.gm1 * uu);
+        const float ib = 0.5f * bsq * rcpf_fast(C.gm1 * uu);
         const float ib2 = ib * ib;
-        const float trat = (C.Rhigh + C.Rlow * ib2) / (1.0f + ib2);
-        thetae = C.mpme * C.gm1 * (uu / rho) / (1.0f + trat);
+        const float trat = (C.Rhigh + C.Rlow * ib2) * rcpf_fast(1.0f + ib2);
+        thetae = C.mpme * C.gm1 * uu * rcpf_fast(rho * (1.0f + trat));
     }
     p.thetae = thetae;
-    if (!(rho > 0.0f) || bsq / rho > C.sigma_cut || r > C.rmax) p.ne = 0.0f;
+    if (!(rho > 0.0f) || bsq > C.sigma_cut * rho || r > C.rmax) p.ne = 0.0f;
     return 1;
 }
 
@@ -290,12 +360,13 @@ KRT_HD void bessel_ratios_f(const float* __restrict__ tab, float x, float& k0k2,
     if (x > 700.0f) {
         // leading terms of the asymptotic series: K0/K2 ~ (1 - 1/(8x)) / (1 + 15/(8x)),
         // K1/K2 ~ (1 + 3/(8x)) / (1 + 15/(8x)), with the next order included
-        const float ix = 1.0f / x;
+        const float ix = rcpf_fast(x);
         const float s0 = 1.0f - 0.125f * ix + 0.0703125f * ix * ix;
         const float s1 = 1.0f + 0.375f * ix - 0.1171875f * ix * ix;
         const float s2 = 1.0f + 1.875f * ix + 0.8203125f * ix * ix;
-        k0k2 = s0 / s2;
-        k1k2 = s1 / s2;
+        const float is2 = rcpf_fast(s2);
+        k0k2 = s0 * is2;
+        k1k2 = s1 * is2;
         return;
     }
     if (x < 1e-8f) {
@@ -335,43 +406,47 @@ KRT_HD float thermal_f(const F32Consts& C, const float* __restrict__ tab, float 
     for (int k = 0; k < 5; ++k) out[k] = 0.0f;
     if (!(ne > 0.0f) || !(thetae > 0.0f) || !(B > 0.0f) || !(gz > 0.0f)) return 0.0f;
     cth = cth > 1.0f ? 1.0f : (cth < -1.0f ? -1.0f : cth);
-    const float sth = sqrtf(1.0f - cth * cth);
+    const float sth = sqrtf_fast(1.0f - cth * cth);
     const float nuB = (float)kNuBPerB * B;
-    const float iTh = 1.0f / thetae;
+    const float iTh = rcpf_fast(thetae);
     float k0k2, k1k2;
     bessel_ratios_f(tab, iTh, k0k2, k1k2);
-    const float ig = 1.0f / gz;
+    const float ig = rcpf_fast(gz);
     const float ig2 = ig * ig;
     out[4] = C.cRV * ne * nuB * cth * ig2 * k0k2;
     if (sth < 1e-10f) return 0.0f;
     out[3] = C.cRQ * ne * nuB * nuB * sth * sth * ig2 * ig * (k1k2 + 6.0f * thetae);
     const float nuc = 1.5f * nuB * sth * thetae * thetae;
-    const float x13 = cbrtf(C.nu_cam * gz / nuc);
-    const float xm13 = 1.0f / x13;
+    // x^(-1/3) and x^(1/3) = x x^(-2/3), x = nu / nu_c
+    // (capped at 1e30, where the emission is zero already: keeps the cube root finite)
+    const float xx = fminf(C.nu_cam * gz * rcpf_fast(nuc), 1e30f);
+    const float xm13 = rcbrtf_fast(xx);
     const float xm23 = xm13 * xm13;
-    const float ex = expf(-1.8899f * x13);
+    const float x13 = xx * xm23;
+    const float ex = expf_fast(-1.8899f * x13);
     const float II = 2.5651f * (1.0f + 1.92f * xm13 + 0.9977f * xm23) * ex;
     const float IQ = 2.5651f * (1.0f + 0.93193f * xm13 + 0.499873f * xm23) * ex;
-    const float IV = (1.81348f * xm23 * xm13 + 3.42319f * xm23 + 0.0292545f * xm13 * sqrtf(xm13) +
+    const float IV = (1.81348f * xm23 * xm13 + 3.42319f * xm23 + 0.0292545f * xm13 * sqrtf_fast(xm13) +
                       2.03773f * xm13) * ex;
     const float pre = C.cJ * ne * gz * iTh * iTh;
     const float jI = pre * II;
     float jQ = pre * IQ;
-    float jV = pre * (4.0f / 3.0f) * (cth / sth) * iTh * IV;
+    float jV = pre * (4.0f / 3.0f) * (cth * rcpf_fast(sth)) * iTh * IV;
     const float jP = hypotf(jQ, jV);
     if (jP > jI) {
         const float sc = jI / jP;
         jQ *= sc;
         jV *= sc;
     }
-    const float em1 = expm1f(C.cHnu * gz * iTh);
-    const float Bnu = C.cBnu * gz * gz * gz / em1;
+    const float em1 = expm1f_fast(C.cHnu * gz * iTh);
+    const float iem1 = rcpf_fast(em1);
+    const float Bnu = C.cBnu * gz * gz * gz * iem1;
     if (jI > 0.0f && Bnu > 0.0f) {
-        const float iB = 1.0f / Bnu;
+        const float iB = rcpf_fast(Bnu);
         out[0] = jI * iB;
         out[1] = jQ * iB;
         out[2] = jV * iB;
-        return out[0] > 0.0f ? C.cSeq / em1 : 0.0f;
+        return out[0] > 0.0f ? C.cSeq * iem1 : 0.0f;
     }
     return 0.0f;
 }
@@ -387,7 +462,7 @@ KRT_HD void fluid_legs_f(const MetricF& g, const float u[4], const float K[4], c
     float e3[4], l3[4], ul[4];
     for (int k = 0; k < 4; ++k) e3[k] = K[k] + Ku * u[k];
     lower_f(g, e3, l3);
-    const float i3 = 1.0f / sqrtf(e3[0] * l3[0] + e3[1] * l3[1] + e3[2] * l3[2] + e3[3] * l3[3]);
+    const float i3 = rsqrtf_fast(e3[0] * l3[0] + e3[1] * l3[1] + e3[2] * l3[2] + e3[3] * l3[3]);
     for (int k = 0; k < 4; ++k) {
         e3[k] *= i3;
         l3[k] *= i3;
@@ -411,7 +486,7 @@ KRT_HD void fluid_legs_f(const MetricF& g, const float u[4], const float K[4], c
             if (vv >= 1e-12f * cn2) break;
         }
     }
-    const float iv = 1.0f / sqrtf(vv);
+    const float iv = rsqrtf_fast(vv);
     for (int k = 0; k < 4; ++k) e2[k] = v[k] * iv;
     lower_f(g, e2, l2);
     const float sg = g.Sig * g.s;
@@ -445,24 +520,26 @@ KRT_HD void mueller_delta_f(float Seq, float tau, float AQ, float AV, float RQ, 
     }
     // invariants, computed on the generator scaled by sc so that they stay in range
     const float sc = fmaxf(1.0f, fmaxf(tau, fabsf(RQ) + fabsf(RV)));
-    const float isc = 1.0f / sc;
+    const float isc = rcpf_fast(sc);
     const float aq = AQ * isc, av = AV * isc, rq = RQ * isc, rv = RV * isc;
     const float a2 = aq * aq + av * av, r2 = rq * rq + rv * rv, ar = aq * rq + av * rv;
     const float q = 0.5f * (a2 - r2);
-    const float rad = sqrtf(q * q + ar * ar);
+    const float rad = sqrtf_fast(q * q + ar * ar);
     float Xs, Ys;
     if (q >= 0.0f) {
         Xs = rad + q;
-        Ys = (Xs > 0.0f) ? ar * ar / Xs : 0.0f;
+        // Y = ar^2 / X <= |ar| <= X: below 1e-30 it is dropped (the hardware
+        // reciprocal does not take subnormal inputs)
+        Ys = (Xs > 1e-30f) ? ar * ar * rcpf_fast(Xs) : 0.0f;
     } else {
         Ys = rad - q;
-        Xs = (Ys > 0.0f) ? ar * ar / Ys : 0.0f;
+        Xs = (Ys > 1e-30f) ? ar * ar * rcpf_fast(Ys) : 0.0f;
     }
     const float X = Xs * sc * sc, Y = Ys * sc * sc;
     const float XY = X + Y;
     float omd0, d1, d2, d3;
     if (XY < 0.1f) {
-        const float et = expf(-tau);
+        const float et = expf_fast(-tau);
         const float Z = -Y;
         float h = 1.0f, zk = 1.0f;
         float c2 = 0.0f, c3 = 0.0f, s0 = 0.0f, s1 = 0.0f;
@@ -476,26 +553,26 @@ KRT_HD void mueller_delta_f(float Seq, float tau, float AQ, float AV, float RQ, 
             h = X * h + zk;
         }
         const float XZ = X * Z;
-        omd0 = -expm1f(-tau) + et * XZ * s0;
+        omd0 = -expm1f_fast(-tau) + et * XZ * s0;
         d1 = et * (1.0f - XZ * s1);
         d2 = et * c2;
         d3 = et * c3;
     } else {
-        const float x = sqrtf(X), y = sqrtf(Y);
-        const float u = expf(0.5f * (x - tau)), v = expf(-0.5f * (x + tau));
+        const float x = sqrtf_fast(X), y = sqrtf_fast(Y);
+        const float u = expf_fast(0.5f * (x - tau)), v = expf_fast(-0.5f * (x + tau));
         const float ep = u * u, em = v * v, et = u * v;
         const float ch = 0.5f * (ep + em);
-        const float shx = (x > 1e-4f) ? 0.5f * (ep - em) / x : et;
+        const float shx = (x > 1e-4f) ? 0.5f * (ep - em) * rcpf_fast(x) : et;
         float sy, cy;
         sincosf(y, &sy, &cy);
-        const float syy = (y > 1e-4f) ? sy / y : 1.0f;
-        const float iXY = 1.0f / XY;
+        const float syy = (y > 1e-4f) ? sy * rcpf_fast(y) : 1.0f;
+        const float iXY = rcpf_fast(XY);
         d1 = (Y * shx + X * et * syy) * iXY;
         d2 = (ch - et * cy) * iXY;
         d3 = (shx - et * syy) * iXY;
         const float qh = 0.5f * (u - v);
-        const float s2h = (cy > 0.0f) ? sy * sy / (2.0f * (1.0f + cy)) : 0.5f * (1.0f - cy);
-        omd0 = -expm1f(-tau) + 2.0f * (X * et * s2h - Y * qh * qh) * iXY;
+        const float s2h = (cy > 0.0f) ? sy * sy * rcpf_fast(2.0f * (1.0f + cy)) : 0.5f * (1.0f - cy);
+        omd0 = -expm1f_fast(-tau) + 2.0f * (X * et * s2h - Y * qh * qh) * iXY;
     }
     float T[4], U[4];
     for (int k = 0; k < 4; ++k) T[k] = d3 * D[k];

@@ -586,10 +586,9 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles
         const float Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
         const float gz = -Ku;  // nu / nu_cam
         const float bb = dot_f(g, p.b, p.b);
-        const float bn = bb > 0.0f ? sqrtf(bb) : 0.0f;
-        const float cth =
-            bn > 0.0f ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (bn * gz)
-                      : 0.0f;
+        const float cth = bb > 1e-30f ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) *
+                                          rsqrtf_fast(bb) * rcpf_fast(gz)
+                                    : 0.0f;
         float co[5];
         const float seq = thermal_f(C, A.btab_f, p.ne, p.thetae, p.B, gz, cth, co);
         if (co[0] != 0.0f || co[1] != 0.0f || co[2] != 0.0f || co[3] != 0.0f || co[4] != 0.0f) {
