@@ -60,6 +60,28 @@ KRT_HD double rsqrt_fast(double x) {
 #endif
 }
 
+// sqrt(x) from the reciprocal square root estimate: one Goldschmidt step for
+// sqrt and 1/(2 sqrt) together, then one residual correction (within about an
+// ulp; the correctly rounded expansion adds a second correction and scaling
+// for subnormal arguments: 20 instructions instead of 8).  Arguments at or
+// below 1e-290 give 0 (their roots change no term where this is used),
+// negative and NaN arguments NaN.
+KRT_HD double sqrt_fast(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const bool big = x > 1e-290;
+    const double xs = big ? x : 1.0;
+    const double y = __builtin_amdgcn_rsq(xs);
+    double s = xs * y, h = 0.5 * y;
+    const double e = fma(-s, h, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    s = fma(fma(-s, s, xs), h, s);
+    return big ? s : (x >= 0.0 ? 0.0 : __builtin_nan(""));
+#else
+    return sqrt(x);
+#endif
+}
+
 // sin and cos of a polar angle th in [0, pi]: th is reduced to t in
 // [-pi/4, pi/4] around 0, pi/2 or pi (exactly, by Sterbenz's lemma, with the
 // low part of pi/2 added after), and sin t, cos t are their Taylor series
@@ -145,7 +167,7 @@ KRT_HD double log_pos(double x) {
 KRT_HD double expm1_small(double x) {
     if (fabs(x) < 0.015625)
         return x * (1.0 + x * (0.5 + x * (1.0 / 6.0 + x * (1.0 / 24.0 + x * (1.0 / 120.0 +
-                                                                       x * (1.0 / 720.0 + x * 1.0 / 5040.0))))));
+                                                                       x * (1.0 / 720.0 + x * (1.0 / 5040.0)))))));
     return expm1(x);
 }
 
@@ -484,7 +506,7 @@ KRT_HD bool adaf_plasma(const AdafDesc& ad, double a, double m, double r, const 
     const double sr = r * irs, ir = irs * irs;
     p.ne = ad.n0 * (ir * irs) * exp(-c * c * ad.i2h2);
     p.thetae = (kKB / (kME * kC * kC)) * ad.T0 * ir;
-    p.B = sqrt((8.0 * kPi * kMP * kC * kC / 6.0) * p.ne * ir * ad.ibeta);
+    p.B = sqrt_fast((8.0 * kPi * kMP * kC * kC / 6.0) * p.ne * ir * ad.ibeta);
     double Om = 0.0, norm = 1.0;
     const bool kepler = (m != 0.0) && (r >= ad.risco);
     if (kepler) {
@@ -610,7 +632,7 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     const double Bv[4] = {0.0, P[5] * r, P[6] * J2, P[7]};
     // g_ij U^i U^j (spatial part)
     const double q = g.rr * U[1] * U[1] + 2.0 * g.rp * U[1] * U[3] + g.hh * U[2] * U[2] + g.pp * U[3] * U[3];
-    const double gamma = sqrt(1.0 + q);
+    const double gamma = sqrt_fast(1.0 + q);
     const double lapse = rsqrt_fast(-g.Itt);
     p.u[0] = gamma * (-g.Itt * lapse);   // gamma / lapse
     p.u[1] = U[1] - gamma * lapse * g.Itr;
@@ -626,8 +648,8 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     p.b[3] = (Bv[3] + bt * p.u[3]) * iut;
     const double bsq = dot(g, p.b, p.b);
     p.bb = bsq;
-    p.B = sqrt(bsq > 0.0 ? bsq : 0.0) * s.B_unit;
-    p.ne = rho * s.rho_unit / (kMP + kME);
+    p.B = sqrt_fast(bsq > 0.0 ? bsq : 0.0) * s.B_unit;
+    p.ne = rho * s.rho_unit * (1.0 / (kMP + kME));
     double thetae = 0.0;
     if (rho > 0.0 && uu > 0.0) {
         // 1/beta = (b.b/2) / ((gamma_ad - 1) u); T_i/T_e = (R_high + R_low / beta^2) / (1 + 1/beta^2)
@@ -781,7 +803,7 @@ KRT_HD double thermal_coefficients(const double* __restrict__ btab, double ne, d
     const double II = 2.5651 * (1.0 + 1.92 * xm13 + 0.9977 * xm23) * ex;
     const double IQ = 2.5651 * (1.0 + 0.93193 * xm13 + 0.499873 * xm23) * ex;
     // x^-1 = xm13^3, x^-1/2 = xm13^(3/2)
-    const double IV = (1.81348 * xm23 * xm13 + 3.42319 * xm23 + 0.0292545 * xm13 * sqrt(xm13) +
+    const double IV = (1.81348 * xm23 * xm13 + 3.42319 * xm23 + 0.0292545 * xm13 * sqrt_fast(xm13) +
                        2.03773 * xm13) * ex;
     const double pre = kJIFac * ne * nu * iTh * iTh;
     double jI = pre * II;
@@ -851,7 +873,7 @@ KRT_HD void mueller_thermal(double Seq, double AI, double AQ, double AV, double 
     const double r2 = (RQ * RQ + RV * RV) * w * w;
     const double ar = (AQ * RQ + AV * RV) * w * w;
     const double q = 0.5 * (a2 - r2);
-    const double rad = sqrt(q * q + ar * ar);
+    const double rad = sqrt_fast(q * q + ar * ar);
     double X, Y;  // x^2 and y^2
     // (the smaller invariant is at most the larger one: below 1e-290 it is
     // taken as 0, which keeps the hardware reciprocal off subnormal inputs)
@@ -1067,11 +1089,11 @@ KRT_HD void fluid_legs(const Metric& g, const double u[4], const double K[4], co
         double vn;
         for (int c = 0; c < 2; ++c) {
             const int dir = (c == 0) ? 2 : 1;
-            const double cn = sqrt(dir == 2 ? g.hh : g.rr);
+            const double cn = sqrt_fast(dir == 2 ? g.hh : g.rr);
             const double pu = ul[dir], p3 = l3[dir];
             for (int k = 0; k < 4; ++k) v[k] = ((k == dir) ? 1.0 : 0.0) + pu * u[k] - p3 * e3[k];
             vv = dot(g, v, v);
-            vn = vv > 0.0 ? sqrt(vv) : 0.0;
+            vn = vv > 0.0 ? sqrt_fast(vv) : 0.0;
             if (vn >= 1e-10 * cn) break;
         }
     }

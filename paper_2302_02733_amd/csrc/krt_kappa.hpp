@@ -392,7 +392,7 @@ KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double A
         b2 = u2;
         b3 = u3;
     } else {
-        const double x = sqrt(X), y = sqrt(Y);
+        const double x = sqrt_fast(X), y = sqrt_fast(Y);
         const double u = exp(0.5 * (x - tau)), v = exp(-0.5 * (x + tau));
         const double ep = u * u, emx = v * v;
         const double ch = 0.5 * (ep + emx);

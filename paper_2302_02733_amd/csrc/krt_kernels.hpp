@@ -418,7 +418,7 @@ KRT_HD int kappa_point(const TraceArgs& A, const double pt[kPointDoubles], Plasm
     const double Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
     nu = A.cam.freq * (-Ku);
     const double bb = p.bb;
-    cth = bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
+    cth = bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt_fast(bb) * (-Ku)) : 0.0;
     return 1;
 }
 
@@ -468,7 +468,7 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[kPointDoubl
         const double nu = A.cam.freq * (-Ku);
         const double bb = p.bb;
         const double cth =
-            bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt(bb) * (-Ku)) : 0.0;
+            bb > 0.0 ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) / (sqrt_fast(bb) * (-Ku)) : 0.0;
         double X, sth;
         if (kappa_frame(p.ne, p.thetae, p.B, nu, cth, X, sth)) {
             double I[8];
