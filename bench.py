@@ -34,10 +34,10 @@ if ROOT not in sys.path:
 # its FP32 and FP64 operations (without packed FP32 both run at the same
 # per-lane rate, so the FP64 peak applies to their sum).
 FLOPS_PER_RAY_STEP = {
-    ("adaf", "fp64"): 2606.0,
-    ("adaf", "fp32"): 2666.0,
-    ("snapshot", "fp64"): 2434.7,
-    ("snapshot", "fp32"): 2379.0,
+    ("adaf", "fp64"): 2593.9,
+    ("adaf", "fp32"): 2320.5,
+    ("snapshot", "fp64"): 2419.1,
+    ("snapshot", "fp32"): 2073.5,
 }
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 
@@ -46,7 +46,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 # divided by the launch's ray-steps (null where not measured on the current
 # kernel).  The algorithmic traffic is the stored path: 64 B written and 64 B
 # read back per point.
-TRAFFIC_BYTES_PER_RAY_STEP = {"adaf1024": 128.3, "snap2048": 133.6}
+TRAFFIC_BYTES_PER_RAY_STEP = {"adaf1024": 128.3, "snap2048": 133.5}
 ALGO_BYTES_PER_RAY_STEP = 128.0
 HBM_PEAK_GBS = 8000.0
 

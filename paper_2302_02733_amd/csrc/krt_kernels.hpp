@@ -529,11 +529,18 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[kPointDoubl
 KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles], int n, bool first,
                                XferStateF& st, Coh& N) {
     const F32Consts& C = A.f32;
-    // sin and cos of theta from an argument reduced in FP64 toward the nearer pole
+    // sin and cos of theta: the argument reduced in FP64 to [0, pi/4] (toward
+    // the nearer pole, then about pi/2), Taylor series in FP32 (through t^9
+    // and t^10: truncation below 2e-10 for t <= pi/4)
     const double thd = pt[1];
     const bool south = thd > 0.5 * kPi;
-    float s, c;
-    sincosf((float)(south ? kPi - thd : thd), &s, &c);
+    const double t0 = south ? kPi - thd : thd;
+    const bool upper = t0 > 0.25 * kPi;
+    const float t = (float)(upper ? 0.5 * kPi - t0 : t0), t2 = t * t;
+    const float sn_t = t * (1.0f + t2 * (-1.0f / 6.0f + t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f + t2 * (1.0f / 362880.0f)))));
+    const float cs_t = 1.0f + t2 * (-0.5f + t2 * (1.0f / 24.0f + t2 * (-1.0f / 720.0f + t2 * (1.0f / 40320.0f + t2 * (-1.0f / 3628800.0f)))));
+    const float s = upper ? cs_t : sn_t;
+    float c = upper ? sn_t : cs_t;
     if (south) c = -c;
     const float r = (float)pt[0];
     const float K[4] = {(float)pt[3], (float)pt[4], (float)pt[5], (float)pt[6]};
