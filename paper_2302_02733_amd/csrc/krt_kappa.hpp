@@ -201,9 +201,9 @@ constexpr double kKapC0 = 1.7320508075688772 * kE * kE * kE / (4.0 * kPi * kME *
 KRT_HD bool kappa_frame(double ne, double w, double B, double nu, double cth, double& X, double& sth) {
     if (!(ne > 0.0) || !(w > 0.0) || !(B > 0.0) || !(nu > 0.0)) return false;
     cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
-    sth = sqrt(1.0 - cth * cth);
+    sth = sqrt_fast(1.0 - cth * cth);
     const double nuc = 1.5 * kNuBPerB * B * sth * w * w;
-    X = (nuc > 0.0) ? nu / nuc : 1e300;
+    X = (nuc > 1e-290) ? nu * rcp_fast(nuc) : 1e300;
     if (!(X < 1e300)) X = 1e300;
     return true;
 }
@@ -212,7 +212,7 @@ KRT_HD void kappa_physical(const double I[8], double ne, double B, double nu, do
                            double out[8]) {
     cth = cth > 1.0 ? 1.0 : (cth < -1.0 ? -1.0 : cth);
     const double nuB = kNuBPerB * B;
-    const double inu = 1.0 / nu;
+    const double inu = rcp_fast(nu);
     out[7] = kRhoVFac * ne * nuB * cth * inu * inu * I[7];
     if (sth < 1e-10) {
         for (int k = 0; k < 7; ++k) out[k] = 0.0;
@@ -220,19 +220,20 @@ KRT_HD void kappa_physical(const double I[8], double ne, double B, double nu, do
     }
     out[6] = 0.5 * kRhoVFac * ne * nuB * nuB * sth * sth * inu * inu * inu * I[6];
     const double pre = ne * kKapC0 * B * sth;
-    const double cv = (4.0 / 3.0) * cth / sth;
+    const double cv = (4.0 / 3.0) * cth * rcp_fast(sth);
     double jI = pre * I[0], jQ = pre * I[1], jV = pre * cv * I[2];
     const double ab = 0.5 * inu * inu / kME;
     double aI = pre * ab * I[3], aQ = pre * ab * I[4], aV = pre * ab * cv * I[5];
-    const double jP = hypot(jQ, jV);
-    if (jP > jI) {
-        const double sc = jI / jP;
+    // clamp |j_P| <= j_I and |a_P| <= a_I, compared in squares where they
+    // stay normal numbers (hypot elsewhere)
+    const bool sqj = jI > 1e-140 && jI < 1e140, sqa = aI > 1e-140 && aI < 1e140;
+    if (sqj ? (jQ * jQ + jV * jV > jI * jI) : (hypot(jQ, jV) > jI)) {
+        const double sc = jI / hypot(jQ, jV);
         jQ *= sc;
         jV *= sc;
     }
-    const double aP = hypot(aQ, aV);
-    if (aP > aI) {
-        const double sc = aI / aP;
+    if (sqa ? (aQ * aQ + aV * aV > aI * aI) : (hypot(aQ, aV) > aI)) {
+        const double sc = aI / hypot(aQ, aV);
         aQ *= sc;
         aV *= sc;
     }
@@ -294,10 +295,11 @@ struct LdsLaneTab {
 
 // t: double[22] or LdsLaneTab.
 template <class Tab>
-KRT_HD void phi1_taylor(double z, Tab& t) {
+KRT_HD void phi1_taylor(double z, double em1, Tab& t) {
+    // em1 = e^z - 1 from the caller
     const double tau = -z;
-    const double ez = exp(z);
-    t[0] = (tau > 0.0) ? expm1(z) / z : 1.0;
+    const double ez = 1.0 + em1;
+    t[0] = (tau > 1e-200) ? em1 * rcp_fast(z) : 1.0;
     if constexpr (std::is_array<Tab>::value) {
         // a register table: fixed indices only.  Downward for every tau, the
         // values at n <= tau replaced by the upward ones
@@ -355,9 +357,9 @@ KRT_HD void mueller_general(double JI, double JQ, double JV, double AI, double A
     }
     const double XY = X + Y;
     const double Z = -Y;
-    phi1_taylor(-tau, t);
-    const double em1 = expm1(-tau);
+    const double em1 = expm1_small(-tau);
     const double et = 1.0 + em1;
+    phi1_taylor(-tau, em1, t);
     // exp(-K w) = d0 + d1 G + d2 G^2 + d3 G^3 and phi1(-K w) = b0 + b1 G + b2 G^2 + b3 G^3
     double d0, d1, d2, d3, b0, b1, b2, b3;
     if (XY < 0.1) {
