@@ -71,6 +71,41 @@ def hbm_roof(ray_steps, kernel_ms):
             "bytes_per_ray_step": ALGO_BYTES_PER_RAY_STEP}
 
 
+def fma_probe(waves_per_simd=4, chains=8, iters=1 << 14, reps=3):
+    """Sustained FP64 FMA throughput of the device (krt_probe_fma): 256 x
+    waves_per_simd blocks of 256 threads, `chains` independent FMA chains per
+    thread; the best of `reps` launches after one warm-up, in TFLOP/s (FMA = 2)."""
+    from paper_2302_02733_amd import krt
+    blocks = 256 * waves_per_simd
+    flops = blocks * 256.0 * iters * 16 * chains * 2
+    with krt.Context(0) as ctx:
+        ctx.probe_fma(blocks, iters, chains)
+        ms = min(ctx.probe_fma(blocks, iters, chains) for _ in range(reps))
+    return {"waves_per_simd": waves_per_simd, "chains": chains, "kernel_ms": ms,
+            "tflops": flops / (ms * 1e-3) / 1e12, "frac_of_published_peak": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+
+
+def copy_probe(nbytes=1 << 30, reps=3):
+    """Device-to-device copy bandwidth (read + write bytes over the copy's
+    time, HIP events), the best of `reps` copies after one warm-up."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return {"bytes": 2 * nbytes, "ms": best, "gbs": 2 * nbytes / (best * 1e-3) / 1e9,
+            "frac_of_published_peak": 2 * nbytes / (best * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def _progress(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -438,11 +473,18 @@ def main():
                     help="the tracer's divergence-free probe over pixels of --workload (for counters)")
     ap.add_argument("--probe-sample", type=int, default=4096)
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--fma-probe", action="store_true",
+                    help="FP64 FMA throughput by independent chains (1, 2, 4, 8) and waves per SIMD (1-4)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: the tracer runs on one GPU (it has no multi-GPU mode); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.fma_probe:
+        for wps in (1, 2, 3, 4):
+            for ch in (1, 2, 4, 8):
+                print(json.dumps({"probe": "fma", **fma_probe(wps, ch)}), flush=True)
+        return
     if args.flop_probe or args.copy_probe:
         run_probe("flop" if args.flop_probe else "copy", args.workload, args.precision, args.probe_sample)
         return
@@ -552,6 +594,13 @@ def main():
         line["vs_fp64"] = vs64
     if args.workload == "adaf1024" and not f32 and not args.no_companions:
         line.update(companions(args, stokes))
+        # the ceilings measured on this device: FP64 FMA issue (eight chains,
+        # four waves per SIMD) and a device copy
+        fp = fma_probe()
+        line["fp64_fma_probe"] = fp
+        line["roofline"]["frac_of_measured_peak"] = line["roofline"]["achieved"] / fp["tflops"]
+        line["copy_probe"] = copy_probe()
+        _progress(f"probes: FP64 FMA {fp['tflops']:.1f} TFLOP/s, copy {line['copy_probe']['gbs']:.0f} GB/s")
     del stokes, status, prims
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, snap_host)

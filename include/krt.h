@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define KRT_ABI_VERSION 7
+#define KRT_ABI_VERSION 8
 
 typedef enum {
     KRT_OK = 0,
@@ -340,6 +340,19 @@ krt_status krt_reduce_noalloc(krt_ctx* ctx, const double* d_stokes, const krt_ca
 /* Message of the last error on this context (never NULL; owned by the
  * context, valid until its next call). */
 const char* krt_last_error(const krt_ctx* ctx);
+
+/* Measurement probe of the device's FP64 FMA issue rate, the ceiling the
+ * tracer's roofline is set against (Sec. 2.2 compares the codes' speed; the
+ * published 78.6 TFLOP/s assumes 2.4 GHz and full issue): blocks blocks of
+ * 256 threads, each thread running iters rounds of 16 dependent FMA steps on
+ * each of `chains` independent FP64 accumulators (chains 1, 2, 4 or 8), so
+ * the launch performs blocks x 256 x iters x 16 x chains FMAs.  A grid of
+ * 256 k blocks puts k waves on each SIMD.  Writes the kernel time in ms
+ * (events on the context's stream) to out_ms.  Allocates and frees a
+ * blocks-double buffer.  Synchronous.  Errors: KRT_E_INVAL (blocks outside
+ * 1..2^20, iters outside 1..2^24, other chain counts, out_ms NULL),
+ * KRT_E_NOMEM, KRT_E_HIP. */
+krt_status krt_probe_fma(krt_ctx* ctx, int32_t blocks, int32_t iters, int32_t chains, double* out_ms);
 
 /* ---- host-only checks (no device needed) ---- */
 

@@ -1376,6 +1376,44 @@ krt_status krt_kappa_integrals(krt_ctx* ctx, int64_t n, const double* d_in, doub
     return KRT_OK;
 }
 
+krt_status krt_probe_fma(krt_ctx* ctx, int32_t blocks, int32_t iters, int32_t chains, double* out_ms) {
+    if (!ctx) return KRT_E_INVAL;
+    if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 24) || !out_ms ||
+        (chains != 1 && chains != 2 && chains != 4 && chains != 8))
+        return fail(ctx, KRT_E_INVAL, "probe needs blocks 1..2^20, iters 1..2^24, chains 1, 2, 4 or 8");
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    double* d = nullptr;
+    if (hipMalloc(&d, (size_t)blocks * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, KRT_E_NOMEM, "probe buffer");
+    }
+    // x < 1 and y small: every chain converges to y / (1 - x), finite
+    const double x = 0.999999, y = 1e-6;
+    const hipError_t re = hipEventRecord(ctx->ev[0], ctx->stream);
+    if (re != hipSuccess) {
+        (void)hipFree(d);
+        KRT_HIP(ctx, re);
+    }
+    switch (chains) {
+        case 1: hipLaunchKernelGGL(fma_probe<1>, dim3(blocks), dim3(256), 0, ctx->stream, d, iters, x, y); break;
+        case 2: hipLaunchKernelGGL(fma_probe<2>, dim3(blocks), dim3(256), 0, ctx->stream, d, iters, x, y); break;
+        case 4: hipLaunchKernelGGL(fma_probe<4>, dim3(blocks), dim3(256), 0, ctx->stream, d, iters, x, y); break;
+        default: hipLaunchKernelGGL(fma_probe<8>, dim3(blocks), dim3(256), 0, ctx->stream, d, iters, x, y); break;
+    }
+    const hipError_t le = hipGetLastError();
+    const hipError_t re1 = hipEventRecord(ctx->ev[1], ctx->stream);
+    const hipError_t se = re1 == hipSuccess ? hipEventSynchronize(ctx->ev[1]) : re1;
+    float ms = 0.0f;
+    const hipError_t te = (le == hipSuccess && se == hipSuccess) ? hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1])
+                                                                  : hipSuccess;
+    (void)hipFree(d);
+    KRT_HIP(ctx, le);
+    KRT_HIP(ctx, se);
+    KRT_HIP(ctx, te);
+    *out_ms = ms;
+    return KRT_OK;
+}
+
 krt_status krt_mueller_general(krt_ctx* ctx, int64_t n, const double* d_coef, const double* d_S, double w,
                                double* d_out) {
     if (!ctx) return KRT_E_INVAL;

@@ -1366,6 +1366,25 @@ __global__ void hook_coeffs(const double* btab, int64_t n, const double* in, dou
     for (int q = 0; q < 8; ++q) out[k * 8 + q] = c[q];
 }
 
+// FP64 FMA issue probe: each thread advances `kChains` independent FMA chains
+// iters x 16 steps; thread 0 of a block writes its sum (the chains stay live).
+template <int kChains>
+__global__ __launch_bounds__(256) void fma_probe(double* out, int iters, double x, double y) {
+    double a[kChains];
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) a[c] = 1e-3 * (double)threadIdx.x + (double)c;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+#pragma unroll
+            for (int c = 0; c < kChains; ++c) a[c] = fma(a[c], x, y);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s += a[c];
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 __global__ void hook_bessel(const double* btab, int64_t n, const double* x, double* out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;

@@ -104,6 +104,8 @@ _SIGS = {
     "krt_set_model_snapshot": (ctypes.c_int, [_P, ctypes.POINTER(SnapshotDesc), _P, ctypes.c_int]),
     "krt_trace": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, ctypes.POINTER(Stats)]),
     "krt_trace_steps": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, _P, _P, ctypes.POINTER(Stats)]),
+    "krt_probe_fma": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_double)]),
     "krt_trace_probe": (ctypes.c_int, [_P, ctypes.POINTER(Camera), _P, ctypes.c_int32, _P,
                                        ctypes.POINTER(Stats)]),
     "krt_reduce": (ctypes.c_int, [_P, _P, ctypes.POINTER(Camera), ctypes.POINTER(ctypes.c_double),
@@ -358,6 +360,14 @@ class Context:
         self._check(lib().krt_trace_probe(self.h, ctypes.byref(c), pix.ctypes.data_as(_P), n, _ptr(stokes),
                                           ctypes.byref(st)))
         return {"stokes": stokes, "stats": st.as_dict()}
+
+    def probe_fma(self, blocks, iters, chains=8):
+        """FP64 FMA issue probe; returns the kernel time in ms (FMAs performed:
+        blocks x 256 x iters x 16 x chains)."""
+        ms = ctypes.c_double(0.0)
+        self._stream()
+        self._check(lib().krt_probe_fma(self.h, int(blocks), int(iters), int(chains), ctypes.byref(ms)))
+        return ms.value
 
     def reduce(self, stokes, cam):
         """Returns (flux_jy[4], I_max); synchronises."""

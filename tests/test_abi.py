@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(krt):
     missing = [s for s in declared_symbols() if not hasattr(L, s)]
     assert not missing
     assert set(declared_symbols()) == set(krt._SIGS)
-    assert krt.lib().krt_abi_version() == 7
+    assert krt.lib().krt_abi_version() == 8
 
 
 def test_struct_layouts_match_header(krt, tmp_path):
