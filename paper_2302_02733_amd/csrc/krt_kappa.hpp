@@ -260,9 +260,10 @@ KRT_HD void kappa_physical(const double I[8], double ne, double B, double nu, do
 // Taylor coefficients of phi1 at z = -tau <= 0: t_n = int_0^1 e^(z s) s^n / n! ds
 // = e^z sum_k tau^k / (n+k+1)!, linked by t_(n-1) = e^z / n! + tau t_n.  The
 // recurrence is used where it is stable: upward, t_n = (t_(n-1) - e^z/n!) / tau,
-// for n <= tau; downward for n > tau, from n = 80 where t_80 is taken as
-// e^z / (81! (1 - tau/82)) (the error this start leaves is damped by tau/n per
-// step, below 1e-20 by n = 21).  Relative error a few ulp for every tau >= 0.
+// for n <= tau; downward for n > tau, from a start n0 far enough above 21
+// where t_n0 is taken as e^z / ((n0+1)! (1 - tau/(n0+2))) (the error this
+// start leaves is damped by tau/n per step).  Relative error a few ulp for
+// every tau >= 0.
 constexpr double kInvFact81 = 1.724992688482352e-121;   // 1/81!
 
 // e^-z t_21 by the downward recurrence in scaled form, s_(n-1) = 1/n! + tau s_n,

@@ -593,6 +593,8 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles
         const float Ku = Kl[0] * p.u[0] + Kl[1] * p.u[1] + Kl[2] * p.u[2] + Kl[3] * p.u[3];
         const float gz = -Ku;  // nu / nu_cam
         const float bb = dot_f(g, p.b, p.b);
+        // (b.b below 1e-30 counts as no field: the hardware reciprocal square
+        // root does not take subnormal inputs)
         const float cth = bb > 1e-30f ? (Kl[0] * p.b[0] + Kl[1] * p.b[1] + Kl[2] * p.b[2] + Kl[3] * p.b[3]) *
                                           rsqrtf_fast(bb) * rcpf_fast(gz)
                                     : 0.0f;

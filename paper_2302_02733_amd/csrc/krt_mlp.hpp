@@ -512,9 +512,10 @@ __device__ __forceinline__ double exp10_out(float y) {
     return __builtin_ldexp((double)__builtin_amdgcn_exp2f((float)(e - k)), (int)k);
 }
 
-// The network for the 64 lanes of a wave: f = this lane's features; on
-// return out[8] = the eight integrals of this lane (log10 destandardised and
-// exponentiated).  Must be called by all 64 lanes together.
+// The network for the 64 lanes of a wave: W = the packed network staged in
+// LDS (its fragments are read through an LDS address), f = this lane's
+// features; on return out[8] = the eight integrals of this lane (log10
+// destandardised and exponentiated).  Must be called by all 64 lanes together.
 __device__ __forceinline__ void mlp_wave(const MlpPacked* __restrict__ W, const float f[4], double out[8]) {
     const int lane = threadIdx.x & 63, hf = lane >> 5;
     float zt[2][4];

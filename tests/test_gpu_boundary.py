@@ -2,7 +2,7 @@
 hook's invariant drift against the oracle's, the errors that must come before
 any launch (no units or model: KRT_E_STATE; a path-store budget of zero:
 KRT_E_NOMEM), non-finite snapshot data (status NONFINITE, counted, no
-crash) and the field-major snapshot layout.
+crash), the field-major snapshot layout and the FP64 FMA probe.
 """
 import os
 
@@ -240,3 +240,20 @@ def test_probe_equals_the_image(krt, snap48, model, f32):
     assert np.array_equal(S, Sp)
     assert stats["rays"] == 64 * len(pix)
     assert stats["total_steps"] == 64 * int(nsp.sum())
+
+
+def test_fma_probe_times_its_launch_and_rejects_bad_arguments(krt):
+    """krt_probe_fma: a positive kernel time for a small launch whose FLOP
+    rate stays below the published FP64 peak; argument errors are KRT_E_INVAL
+    before any launch."""
+    with krt.Context(0) as ctx:
+        blocks, iters = 256, 64
+        for chains in (1, 8):
+            ms = ctx.probe_fma(blocks, iters, chains)
+            tflops = blocks * 256.0 * iters * 16 * chains * 2 / (ms * 1e-3) / 1e12
+            _log(f"fma probe: {chains} chains, {ms:.3f} ms, {tflops:.1f} TFLOP/s")
+            assert ms > 0.0 and tflops < 78.6 * 1.1
+        for bad in ((0, iters, 8), (blocks, 0, 8), (blocks, iters, 3), ((1 << 20) + 1, iters, 8)):
+            with pytest.raises(krt.KrtError) as e:
+                ctx.probe_fma(*bad)
+            assert e.value.code == krt.E_INVAL
