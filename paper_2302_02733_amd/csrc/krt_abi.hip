@@ -698,7 +698,8 @@ krt_status krt_create(int device, krt_ctx** out) {
             st = fail(ctx, KRT_E_NOMEM, "cannot allocate context buffers");
             break;
         }
-        // Bessel-ratio table: node values, then Chebyshev coefficients
+        // Bessel-ratio table: node values, Chebyshev coefficients, then the
+        // same polynomials in monomial form
         double* vals = nullptr;
         if (hipMalloc(&vals, (size_t)kBesPanels * kBesCoef * 2 * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
@@ -709,6 +710,8 @@ krt_status krt_create(int device, krt_ctx** out) {
         hipLaunchKernelGGL(bessel_table_nodes, dim3((nn + 127) / 128), dim3(128), 0, nullptr, vals);
         const int nc = kBesPanels * 2 * kBesCoef;
         hipLaunchKernelGGL(bessel_table_coefs, dim3((nc + 127) / 128), dim3(128), 0, nullptr, vals,
+                           ctx->btab);
+        hipLaunchKernelGGL(bessel_table_monomial, dim3((kBesPanels * 2 + 127) / 128), dim3(128), 0, nullptr,
                            ctx->btab);
         e = hipDeviceSynchronize();
         (void)hipFree(vals);

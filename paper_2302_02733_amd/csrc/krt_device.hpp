@@ -668,10 +668,13 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
 
 // ---------------------------------------------------------------------------
 // Bessel-function ratios K0/K2 and K1/K2 of x = 1/Theta_e.
-// Table: piecewise Chebyshev series of degree kBesDeg in x itself, on panels
+// Table: piecewise polynomials of degree kBesDeg in x itself, on panels
 // that split every binade [2^e, 2^(e+1)) of [2^kBesE0, 2^kBesE1) into
 // kBesSub equal parts, built at context creation from the trapezoid rule on
-// K_nu(x) e^x = int_0^inf exp(-x (cosh s - 1)) cosh(nu s) ds.  A panel and
+// K_nu(x) e^x = int_0^inf exp(-x (cosh s - 1)) cosh(nu s) ds as Chebyshev
+// interpolants and stored as monomial coefficients in the panel variable z
+// (evaluated by Horner's rule, one FMA per degree; the Chebyshev coefficients
+// decay fast enough on these panels that both forms round alike).  A panel and
 // its Chebyshev variable come from the exponent and mantissa bits of x (no
 // logarithm); the ratios are analytic in x away from x = 0, which lies 8 panel
 // half-widths or more from every panel, so degree 12 reaches round-off.
@@ -740,19 +743,13 @@ KRT_HD void bessel_ratios(const double* __restrict__ table, double x,
     const int p = bessel_panel(x, z);
     const double* c0 = table + (size_t)p * 2 * kBesCoef;
     const double* c1 = c0 + kBesCoef;
-    // Clenshaw recurrences
-    const double z2 = 2.0 * z;
-    double b1 = c0[kBesDeg], b2 = 0.0, d1 = c1[kBesDeg], d2 = 0.0;
-    for (int k = kBesDeg - 1; k >= 1; --k) {
-        const double bt = fma(z2, b1, c0[k] - b2);
-        b2 = b1;
-        b1 = bt;
-        const double dt = fma(z2, d1, c1[k] - d2);
-        d2 = d1;
-        d1 = dt;
+    double b = c0[kBesDeg], d = c1[kBesDeg];
+    for (int k = kBesDeg - 1; k >= 0; --k) {
+        b = fma(b, z, c0[k]);
+        d = fma(d, z, c1[k]);
     }
-    k0k2 = fma(z, b1, c0[0] - b2);
-    k1k2 = fma(z, d1, c1[0] - d2);
+    k0k2 = b;
+    k1k2 = d;
 }
 
 // ---------------------------------------------------------------------------

@@ -384,18 +384,13 @@ KRT_HD void bessel_ratios_f(const float* __restrict__ tab, float x, float& k0k2,
     pn = pn < 0 ? 0 : (pn >= kBesPanels ? kBesPanels - 1 : pn);
     const float* c0 = tab + pn * 2 * kBesCoef;
     const float* c1 = c0 + kBesCoef;
-    const float z2 = 2.0f * z;
-    float b1 = c0[kBesDeg], b2 = 0.0f, d1 = c1[kBesDeg], d2 = 0.0f;
-    for (int kk = kBesDeg - 1; kk >= 1; --kk) {
-        const float bt = fmaf(z2, b1, c0[kk] - b2);
-        b2 = b1;
-        b1 = bt;
-        const float dt = fmaf(z2, d1, c1[kk] - d2);
-        d2 = d1;
-        d1 = dt;
+    float b = c0[kBesDeg], d = c1[kBesDeg];
+    for (int kk = kBesDeg - 1; kk >= 0; --kk) {
+        b = fmaf(b, z, c0[kk]);
+        d = fmaf(d, z, c1[kk]);
     }
-    k0k2 = fmaf(z, b1, c0[0] - b2);
-    k1k2 = fmaf(z, d1, c1[0] - d2);
+    k0k2 = b;
+    k1k2 = d;
 }
 
 // Thermal coefficients in FP32 at redshift factor g = nu / nu_cam.  Writes

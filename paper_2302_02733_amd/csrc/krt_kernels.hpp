@@ -1256,6 +1256,32 @@ __global__ void bessel_table_coefs(const double* vals, double* table) {
     table[(size_t)p * 2 * kBesCoef + f * kBesCoef + j] = s;
 }
 
+// Chebyshev coefficients of each (panel, function) series to monomial
+// coefficients in z, in place: T_0 = 1, T_1 = z, T_(j+1) = 2 z T_j - T_(j-1)
+// (integer coefficients, exact in FP64), a_i = sum_j c_j [z^i] T_j.
+__global__ void bessel_table_monomial(double* table) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= kBesPanels * 2) return;
+    double* c = table + (size_t)idx * kBesCoef;
+    double a[kBesCoef], tp[kBesCoef], tc[kBesCoef];
+    for (int i = 0; i < kBesCoef; ++i) {
+        tp[i] = (i == 0) ? 1.0 : 0.0;
+        tc[i] = (i == 1) ? 1.0 : 0.0;
+        a[i] = c[0] * tp[i] + c[1] * tc[i];
+    }
+    for (int j = 2; j < kBesCoef; ++j) {
+        double tn[kBesCoef];
+        tn[0] = -tp[0];
+        for (int i = 1; i < kBesCoef; ++i) tn[i] = 2.0 * tc[i - 1] - tp[i];
+        for (int i = 0; i < kBesCoef; ++i) {
+            a[i] += c[j] * tn[i];
+            tp[i] = tc[i];
+            tc[i] = tn[i];
+        }
+    }
+    for (int i = 0; i < kBesCoef; ++i) c[i] = a[i];
+}
+
 // ---------------------------------------------------------------------------
 // Snapshot layout 1 ([8][ncell], one array per field) to layout 0
 // ([ncell][8], the fields of a cell together, which the gather reads as
