@@ -34,10 +34,10 @@ if ROOT not in sys.path:
 # its FP32 and FP64 operations (without packed FP32 both run at the same
 # per-lane rate, so the FP64 peak applies to their sum).
 FLOPS_PER_RAY_STEP = {
-    ("adaf", "fp64"): 2593.9,
-    ("adaf", "fp32"): 2320.5,
-    ("snapshot", "fp64"): 2419.1,
-    ("snapshot", "fp32"): 2073.5,
+    ("adaf", "fp64"): 2570.9,
+    ("adaf", "fp32"): 2297.5,
+    ("snapshot", "fp64"): 2406.8,
+    ("snapshot", "fp32"): 2061.2,
 }
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 
