@@ -225,6 +225,35 @@ KRT_HD void load_point(const double* p, double v[kPointDoubles]) {
     v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y;
 }
 
+// The FP32-operator mode keeps its points in FP32 (32 B): r, the signed
+// distance to the nearer pole (theta north of the equator, theta - pi south of
+// it, so that sin theta keeps its relative precision at both poles), phi
+// reduced to [0, 2 pi), K^t, K^r, K^theta, K^phi and the step.  Its transfer
+// operators are FP32 already, and the geodesic that writes the points stays
+// FP64.  Slices and chunks of the store keep 64 B per point, half used.
+struct PointF {
+    float r, tp, ph, K[4], d;
+};
+
+KRT_HD void store_point_f32(double* p, const double y[7], double h) {
+    const double tp = y[1] > 0.5 * kPi ? y[1] - kPi : y[1];
+    const double ph = y[2] - (2.0 * kPi) * floor(y[2] * (0.5 / kPi));
+    float4* q = reinterpret_cast<float4*>(p);
+    q[0] = make_float4((float)y[0], (float)tp, (float)ph, (float)y[3]);
+    q[1] = make_float4((float)y[4], (float)y[5], (float)y[6], (float)h);
+}
+
+KRT_HD void load_point_f32(const double* p, PointF& v) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    const float4 a = q[0], b = q[1];
+    v.r = a.x; v.tp = a.y; v.ph = a.z; v.K[0] = a.w;
+    v.K[1] = b.x; v.K[2] = b.y; v.K[3] = b.z; v.d = b.w;
+}
+
+// Distance between consecutive points of the store (doubles) in mode kMode.
+template <int kMode>
+constexpr int kPointStride = kMode == kModeF32 ? 4 : kPointDoubles;
+
 // ---------------------------------------------------------------------------
 // Uniform parameters (spin, mass, camera, plasma model, buffers) are read
 // where they are used.  Kept for the whole persistent kernel they would fill
@@ -526,15 +555,15 @@ KRT_HD void transfer_point_kappa(const TraceArgs& A, const double pt[kPointDoubl
 // FP32, the coherency matrix and the Heun state in FP64, every increment
 // formed in FP32 (scaled by 2^160) and added in FP64.  The radiative update
 // adds the coherency matrix of the Stokes increment on the fluid legs.
-KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles], int n, bool first,
-                               XferStateF& st, Coh& N) {
+KRT_HD void transfer_point_f32(const TraceArgs& A, const PointF& pt, int n, bool first, XferStateF& st,
+                               Coh& N) {
     const F32Consts& C = A.f32;
-    // sin and cos of theta: the argument reduced in FP64 to [0, pi/4] (toward
-    // the nearer pole, then about pi/2), Taylor series in FP32 (through t^9
-    // and t^10: truncation below 2e-10 for t <= pi/4)
-    const double thd = pt[1];
-    const bool south = thd > 0.5 * kPi;
-    const double t0 = south ? kPi - thd : thd;
+    // sin and cos of theta: from the distance t0 to the nearer pole, reduced
+    // in FP64 to [0, pi/4] (about pi/2 beyond pi/4), Taylor series in FP32
+    // (through t^9 and t^10: truncation below 2e-10 for t <= pi/4)
+    const bool south = pt.tp < 0.0f;
+    const double t0 = fabs((double)pt.tp);
+    const double thd = south ? kPi - t0 : t0;
     const bool upper = t0 > 0.25 * kPi;
     const float t = (float)(upper ? 0.5 * kPi - t0 : t0), t2 = t * t;
     const float sn_t = t * (1.0f + t2 * (-1.0f / 6.0f + t2 * (1.0f / 120.0f + t2 * (-1.0f / 5040.0f + t2 * (1.0f / 362880.0f)))));
@@ -542,9 +571,9 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles
     const float s = upper ? cs_t : sn_t;
     float c = upper ? sn_t : cs_t;
     if (south) c = -c;
-    const float r = (float)pt[0];
-    const float K[4] = {(float)pt[3], (float)pt[4], (float)pt[5], (float)pt[6]};
-    const double Dn = (n == 0) ? 0.0 : fabs(pt[7]);
+    const float r = pt.r;
+    const float K[4] = {pt.K[0], pt.K[1], pt.K[2], pt.K[3]};
+    const double Dn = (n == 0) ? 0.0 : fabs((double)pt.d);
     MetricF g;
     MetricDF dr, dh;
     metric_d_f(C.a, C.m, r, s, c, g, dr, dh);
@@ -577,10 +606,10 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const double pt[kPointDoubles
     int pk = 0;
     if (A.model == kModelSnapshot) {
         const SnapDesc& q = A.snap;
-        double X2 = (pt[2] - q.x3s) * q.idx3 - 0.5;
+        double X2 = ((double)pt.ph - q.x3s) * q.idx3 - 0.5;
         X2 -= q.n3 * floor(X2 / q.n3);
         // no plasma beyond the emission radius (n_e = 0: every coefficient zero)
-        if (pt[0] <= q.rmax)
+        if ((double)r <= q.rmax)
             pk = q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
                            : snapshot_plasma_f(C, q.prims, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p);
     } else {
@@ -706,13 +735,14 @@ __device__ __forceinline__ int take_chunk(const TraceArgs& A, int* wchunks, int 
 
 // Address of stored point m of this lane: the wave's slice for m < cap, then
 // the wave's chunks in the order taken.
+// Slices and chunks are laid out for 64 B points; points are kS doubles apart.
+template <int kS>
 __device__ __forceinline__ const double* point_addr(const TraceArgs& A, const double* slot,
                                                    const int* wchunks, int m, int lane) {
-    if (m < A.cap) return slot + ((size_t)m * 64 + lane) * kPointDoubles;
+    if (m < A.cap) return slot + ((size_t)m * 64 + lane) * kS;
     const int k = m / A.cap - 1;
     const int c = wchunks[k];
-    return A.chunk_pool + (size_t)c * A.cap * 64 * kPointDoubles +
-           ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * kPointDoubles;
+    return A.chunk_pool + (size_t)c * A.cap * 64 * kPointDoubles + ((size_t)(m - (k + 1) * A.cap) * 64 + lane) * kS;
 }
 
 // Surrogate and exact-integrator point counts of a wave, added once per tile.
@@ -764,7 +794,7 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
     // waves per SIMD covering the load, it gains nothing.
     constexpr bool kPrefetch = kMode == kModeKapExact;
     double nxt[kPointDoubles] = {};
-    if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr(src(), slot, wchunks, nmax, lane), nxt);
+    if (kPrefetch && nmax >= 0 && nmax <= n_end) load_point(point_addr<kPointDoubles>(src(), slot, wchunks, nmax, lane), nxt);
     for (int m = nmax; m >= 0; --m) {
         const TraceArgs A = src();
         if constexpr (kMode == kModeKapMlp) {
@@ -777,7 +807,7 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
             Plasma p;
             if (m <= n_end) {
                 double pt[kPointDoubles];
-                load_point(point_addr(A, slot, wchunks, m, lane), pt);
+                load_point(point_addr<kPointDoubles>(A, slot, wchunks, m, lane), pt);
                 double nu, cth, sth;
                 pk = kappa_point(A, pt, p, nu, cth);
                 if (pk == 1 && kappa_frame(p.ne, p.thetae, p.B, nu, cth, Xp, sth)) {
@@ -805,26 +835,29 @@ __device__ __forceinline__ void trace_transfer(const Src& src, double* slot, con
             }
             if (m <= n_end) {
                 double pt[kPointDoubles];
-                load_point(point_addr(A, slot, wchunks, m, lane), pt);
+                load_point(point_addr<kPointDoubles>(A, slot, wchunks, m, lane), pt);
                 n_mlp += want ? 1u : 0u;
                 n_exact += fall ? 1u : 0u;
                 transfer_point_kappa<true>(A, pt, m, m == n_end, xs, N, I, want || fall, n_exact, &p, pk);
             }
+        } else if constexpr (kMode == kModeF32) {
+            if (m > n_end) continue;
+            PointF pt;
+            load_point_f32(point_addr<kPointStride<kMode>>(A, slot, wchunks, m, lane), pt);
+            transfer_point_f32(A, pt, m, m == n_end, xs, N);
         } else {
             double pt[kPointDoubles];
             if constexpr (kPrefetch) {
                 // the next point (m - 1) is loaded while this one is processed
 #pragma unroll
                 for (int k = 0; k < kPointDoubles; ++k) pt[k] = nxt[k];
-                if (m >= 1 && m - 1 <= n_end) load_point(point_addr(A, slot, wchunks, m - 1, lane), nxt);
+                if (m >= 1 && m - 1 <= n_end) load_point(point_addr<kPointDoubles>(A, slot, wchunks, m - 1, lane), nxt);
                 if (m > n_end) continue;
             } else {
                 if (m > n_end) continue;
-                load_point(point_addr(A, slot, wchunks, m, lane), pt);
+                load_point(point_addr<kPointDoubles>(A, slot, wchunks, m, lane), pt);
             }
-            if constexpr (kMode == kModeF32)
-                transfer_point_f32(A, pt, m, m == n_end, xs, N);
-            else if constexpr (kMode == kModeKapExact)
+            if constexpr (kMode == kModeKapExact)
                 transfer_point_kappa(A, pt, m, m == n_end, xs, N, nullptr, false, n_exact);
             else
                 transfer_point(A, pt, m, m == n_end, xs, N);
@@ -854,8 +887,9 @@ __device__ __forceinline__ void tile_pixel(int tiles_x, int tile_w, int tile, in
 
 // Geodesic phase of one tile: camera launch and RK4 steps in lockstep, every
 // point stored in the wave's slice, then in chunks of the paged store (kStore),
-// or only the end state kept.  Returns the number of chunks the wave holds.
-template <bool kStore, class Src>
+// or only the end state kept; kCompact: in the FP32-operator mode's format.
+// Returns the number of chunks the wave holds.
+template <bool kStore, bool kCompact, class Src>
 __device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i, int j, double* slot,
                                               int* wchunks, size_t wave, int lane, double& alpha,
                                               double& beta, double y[7], double& hlast, uint8_t& st,
@@ -872,7 +906,13 @@ __device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i,
     }
     double sn, cs;
     sincos_polar(y[1], sn, cs);
-    if (kStore && valid) store_point(slot + (size_t)lane * kPointDoubles, y, 0.0);
+    constexpr int kS = kCompact ? 4 : kPointDoubles;
+    if (kStore && valid) {
+        if constexpr (kCompact)
+            store_point_f32(slot + (size_t)lane * kS, y, 0.0);
+        else
+            store_point(slot + (size_t)lane * kS, y, 0.0);
+    }
 
     st = valid ? kRunning : kEscaped;
     n = 0;
@@ -900,7 +940,11 @@ __device__ __forceinline__ int geodesic_phase(const Src& src, bool valid, int i,
                 cstart += A.cap;
                 cbase = A.chunk_pool + (size_t)id * A.cap * 64 * kPointDoubles;
             }
-            store_point(cbase + ((size_t)(n - cstart) * 64 + lane) * kPointDoubles, y, h);
+            double* p = cbase + ((size_t)(n - cstart) * 64 + lane) * kS;
+            if constexpr (kCompact)
+                store_point_f32(p, y, h);
+            else
+                store_point(p, y, h);
         }
         st = stop_test(A, y, h, n, sn);
     }
@@ -1007,7 +1051,8 @@ __global__ __launch_bounds__(256, kMode == kModeKapExact ? 1 : (kMode == kModeF3
         uint8_t st;
         int n;
         const int nch_w =
-            geodesic_phase<!kGeoOnly>(src, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y, hlast, st, n);
+            geodesic_phase<!kGeoOnly, kMode == kModeF32>(src, valid, i, j, slot, wchunks, wave, lane, alpha, beta, y,
+                                                         hlast, st, n);
         if (kGeoOnly) {
             const TraceArgs A = src();
             if (valid) {
@@ -1132,8 +1177,8 @@ __global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
         double alpha, beta, hlast, y[7];
         uint8_t st;
         int n;
-        const int nch_w = geodesic_phase<true>(BatchSource{base, g, -1}, valid, i, j, slot, wchunks, wave, lane,
-                                               alpha, beta, y, hlast, st, n);
+        const int nch_w = geodesic_phase<true, kMode == kModeF32>(BatchSource{base, g, -1}, valid, i, j, slot,
+                                                                  wchunks, wave, lane, alpha, beta, y, hlast, st, n);
         for (int q = G.inst_begin; q < G.inst_end; ++q)
             trace_transfer<kMode>(BatchSource{base, g, q}, slot, wchunks, lane, valid, pix, alpha, beta, st, n);
         if (lane == 0)
@@ -1142,7 +1187,8 @@ __global__ __launch_bounds__(256, 2) void trace_batch(TraceArgs A) {
 }
 
 // Rays longer than the wave-synchronous store: one ray per lane with a
-// full-length private store ([point][8]); lanes loop over the overflow list
+// full-length private store (64 B per point, the FP32-operator mode's points
+// at its 32 B stride); lanes loop over the overflow list
 // (entries of batch instances carry their instance).
 template <int kMode>
 __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
@@ -1178,7 +1224,11 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
             y[0] = X[1]; y[1] = X[2]; y[2] = X[3];
             y[3] = K[0]; y[4] = K[1]; y[5] = K[2]; y[6] = K[3];
         }
-        store_point(path, y, 0.0);
+        constexpr int kS = kPointStride<kMode>;
+        if constexpr (kMode == kModeF32)
+            store_point_f32(path, y, 0.0);
+        else
+            store_point(path, y, 0.0);
         double sn, cs;
         sincos_polar(y[1], sn, cs);
         uint8_t st = kRunning;
@@ -1186,7 +1236,10 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         while (st == kRunning) {
             const double h = rk4_step(R.cam.a, R.cam.m, R.eps, y, sn, cs);
             ++n;
-            store_point(path + (size_t)n * kPointDoubles, y, h);
+            if constexpr (kMode == kModeF32)
+                store_point_f32(path + (size_t)n * kS, y, h);
+            else
+                store_point(path + (size_t)n * kS, y, h);
             st = stop_test(R, y, h, n, sn);
         }
         const int n_end = (st == kNonFinite || st == kAxis) ? n - 1 : n;
@@ -1194,14 +1247,18 @@ __global__ __launch_bounds__(64) void trace_long(TraceArgs A) {
         Coh N;
         unsigned n_exact = 0;
         for (int m = n_end; m >= 0; --m) {
-            double pt[kPointDoubles];
-            load_point(path + (size_t)m * kPointDoubles, pt);
-            if constexpr (kMode == kModeF32)
-                transfer_point_f32(R, pt, m, m == n_end, xs, N);
-            else if constexpr (kKappa<kMode>)
-                transfer_point_kappa(R, pt, m, m == n_end, xs, N, nullptr, false, n_exact);
-            else
-                transfer_point(R, pt, m, m == n_end, xs, N);
+            if constexpr (kMode == kModeF32) {
+                PointF pf;
+                load_point_f32(path + (size_t)m * kS, pf);
+                transfer_point_f32(R, pf, m, m == n_end, xs, N);
+            } else {
+                double pt[kPointDoubles];
+                load_point(path + (size_t)m * kS, pt);
+                if constexpr (kKappa<kMode>)
+                    transfer_point_kappa(R, pt, m, m == n_end, xs, N, nullptr, false, n_exact);
+                else
+                    transfer_point(R, pt, m, m == n_end, xs, N);
+            }
         }
         if constexpr (kKappa<kMode>) atomicAdd(&A.counters[9], (unsigned long long)n_exact);
         double S[4];
