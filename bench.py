@@ -35,19 +35,25 @@ if ROOT not in sys.path:
 # per-lane rate, so the FP64 peak applies to their sum).
 FLOPS_PER_RAY_STEP = {
     ("adaf", "fp64"): 2570.9,
-    ("adaf", "fp32"): 2297.5,
+    ("adaf", "fp32"): 2300.5,
     ("snapshot", "fp64"): 2406.8,
-    ("snapshot", "fp32"): 2061.2,
+    ("snapshot", "fp32"): 2064.8,
 }
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 
 # HBM bytes per ray-step of trace_waves: rocprofv3 FETCH_SIZE and WRITE_SIZE of
 # one launch, each scaled by what the counter reads for a copy of known size,
 # divided by the launch's ray-steps (null where not measured on the current
-# kernel).  The algorithmic traffic is the stored path: 64 B written and 64 B
-# read back per point.
-TRAFFIC_BYTES_PER_RAY_STEP = {"adaf1024": 128.3, "snap2048": 133.5}
-ALGO_BYTES_PER_RAY_STEP = 128.0
+# kernel).  Per (workload, precision).  The algorithmic traffic is the stored
+# path: each point written once and read back once, 64 B (FP64 points) or 32 B
+# (the FP32-operator mode's FP32 points).
+TRAFFIC_BYTES_PER_RAY_STEP = {
+    ("adaf1024", "fp64"): 128.3,
+    ("snap2048", "fp64"): 133.5,
+    ("adaf1024", "fp32"): 64.2,
+    ("snap2048", "fp32"): 66.2,
+}
+ALGO_BYTES_PER_RAY_STEP = {"fp64": 128.0, "fp32": 64.0}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -64,11 +70,12 @@ def roofline(fprs, ray_steps, kernel_ms, traffic_per_step=None):
             "kernel": "trace_waves", "kernel_ms": kernel_ms, "flops_per_ray_step": fprs}
 
 
-def hbm_roof(ray_steps, kernel_ms):
+def hbm_roof(ray_steps, kernel_ms, precision="fp64"):
     """The path store's algorithmic traffic against the HBM peak."""
-    gbs = ALGO_BYTES_PER_RAY_STEP * ray_steps / (kernel_ms * 1e-3) / 1e9
+    b = ALGO_BYTES_PER_RAY_STEP[precision]
+    gbs = b * ray_steps / (kernel_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "bytes_per_ray_step": ALGO_BYTES_PER_RAY_STEP}
+            "bytes_per_ray_step": b}
 
 
 def fma_probe(waves_per_simd=4, chains=8, iters=1 << 14, reps=3):
@@ -404,7 +411,9 @@ def companions(args, stokes64):
         ctx.set_precision(krt.PRECISION_FP32_TRANSFER)
         r32, s32 = image_measure(ctx, w["camera"], 1, 3)
         r32.update(image_error(s32, stokes64))
-        r32["roofline"] = roofline(flops_per_ray_step("adaf", "fp32"), r32["total_steps"], r32["kernel_ms"])
+        r32["roofline"] = roofline(flops_per_ray_step("adaf", "fp32"), r32["total_steps"], r32["kernel_ms"],
+                                   TRAFFIC_BYTES_PER_RAY_STEP.get(("adaf1024", "fp32")))
+        r32["hbm_roofline"] = hbm_roof(r32["total_steps"], r32["kernel_ms"], "fp32")
         del s32
         out["adaf1024_fp32"] = r32
         _progress(f"adaf1024 fp32: {r32['ms_per_image']:.1f} ms per image")
@@ -419,7 +428,7 @@ def companions(args, stokes64):
         cs.set_model_snapshot(desc, prims)
         rs, ss = image_measure(cs, w["camera"], 1, 2)
         rs["roofline"] = roofline(flops_per_ray_step("snapshot", "fp64"), rs["total_steps"], rs["kernel_ms"],
-                                  TRAFFIC_BYTES_PER_RAY_STEP.get("snap2048"))
+                                  TRAFFIC_BYTES_PER_RAY_STEP.get(("snap2048", "fp64")))
         rs["hbm_roofline"] = hbm_roof(rs["total_steps"], rs["kernel_ms"])
         out["snap2048"] = rs
         _progress(f"snap2048: {rs['ms_per_image']:.1f} ms per image")
@@ -427,7 +436,9 @@ def companions(args, stokes64):
         cs.set_model_snapshot(desc, prims32)
         rs32, ss32 = image_measure(cs, w["camera"], 1, 2)
         rs32.update(image_error(ss32, ss))
-        rs32["roofline"] = roofline(flops_per_ray_step("snapshot", "fp32"), rs32["total_steps"], rs32["kernel_ms"])
+        rs32["roofline"] = roofline(flops_per_ray_step("snapshot", "fp32"), rs32["total_steps"], rs32["kernel_ms"],
+                                    TRAFFIC_BYTES_PER_RAY_STEP.get(("snap2048", "fp32")))
+        rs32["hbm_roofline"] = hbm_roof(rs32["total_steps"], rs32["kernel_ms"], "fp32")
         rs32["speedup_vs_fp64"] = rs["kernel_ms"] / rs32["kernel_ms"]
         out["snap2048_fp32"] = rs32
         _progress(f"snap2048 fp32: {rs32['ms_per_image']:.1f} ms per image")
@@ -564,7 +575,7 @@ def main():
     ray_steps = sum(steps) / len(steps)
     prec = "fp32" if f32 else "fp64"
     roof = roofline(flops_per_ray_step("snapshot" if is_snap else "adaf", prec), ray_steps, kernel_ms,
-                    None if f32 else TRAFFIC_BYTES_PER_RAY_STEP.get(args.workload))
+                    TRAFFIC_BYTES_PER_RAY_STEP.get((args.workload, prec)))
     roof["kernel_ms_median"] = sorted(kms)[len(kms) // 2]
     line = {
         "metric": ("polarized rays/s (FP64 geodesic + FP32-operator polarized transfer, whole image)" if f32
@@ -587,7 +598,7 @@ def main():
         "long_rays": stats["long_rays"],
         "flux_jy": flux,
         "roofline": roof,
-        "hbm_roofline": hbm_roof(ray_steps, kernel_ms),
+        "hbm_roofline": hbm_roof(ray_steps, kernel_ms, prec),
     }
     if vs64 is not None:
         vs64["speedup"] = vs64["fp64_kernel_ms"] / kernel_ms

@@ -24,11 +24,16 @@ def test_roofline_constants():
         assert v is None or 1000.0 < v < 7000.0
     assert bench.FLOPS_PER_RAY_STEP[("adaf", "fp64")] is not None
     assert bench.FP64_PEAK_TFLOPS == 78.6 and bench.HBM_PEAK_GBS == 8000.0
-    # the path's algorithmic traffic is 64 B stored + 64 B read back per point;
-    # measured traffic (when present) is at least that
-    assert bench.ALGO_BYTES_PER_RAY_STEP == 128.0
-    for v in bench.TRAFFIC_BYTES_PER_RAY_STEP.values():
-        assert v is None or 126.0 < v < 400.0
+    # the path's algorithmic traffic is each point stored and read back once:
+    # 64 B points (FP64) or 32 B points (FP32-operator mode); measured traffic
+    # (when present) is at least that
+    assert bench.ALGO_BYTES_PER_RAY_STEP == {"fp64": 128.0, "fp32": 64.0}
+    for (wl, prec), v in bench.TRAFFIC_BYTES_PER_RAY_STEP.items():
+        assert wl in ("adaf1024", "snap2048") and prec in ("fp64", "fp32")
+        a = bench.ALGO_BYTES_PER_RAY_STEP[prec]
+        assert v is None or 0.99 * a < v < 3.0 * a
+    h = bench.hbm_roof(1e9, 100.0, "fp32")
+    assert h["bytes_per_ray_step"] == 64.0 and abs(h["achieved"] - 640.0) < 1e-9
     r = bench.roofline(3000.0, 1e9, 100.0)
     assert abs(r["achieved"] - 30.0) < 1e-9 and abs(r["frac"] - 30.0 / 78.6) < 1e-12
     assert bench.roofline(None, 1e9, 100.0)["frac"] is None
