@@ -101,6 +101,44 @@ def test_f32_snapshot48_image(ctx, prims_f32):
     del t
 
 
+@pytest.mark.parametrize("chunks,expect_long", [("64", "none"), ("0", "some")])
+def test_f32_chunked_and_long_ray_paths(ctx, chunks, expect_long):
+    """The FP32-operator mode's 32 B path points across the paged store: a
+    37 x 23 image with a 700-point wave slice, its paths continued in chunks
+    (64 chunks: no long rays) or, without chunks, traced by the long-ray
+    kernel.  The image equals the one traced with the default slice (same
+    arithmetic on the same points) and meets the mode's bar against the
+    oracle."""
+    import os
+    cam = W.adaf_camera(37, fov=30.0)
+    cam.update(ny=23, fov_y=20.0, seed=12345)
+    ctx.set_units(W.UNITS)
+    ctx.set_model(W.ADAF)
+    So, sto, nso = oracle.render(cam, W.UNITS, W.ADAF)
+    ref = ctx.trace(cam)["stokes"].cpu().numpy()
+    os.environ["KRT_PATH_CAP"] = "700"
+    os.environ["KRT_CHUNKS"] = chunks
+    try:
+        ns = torch.empty((cam["ny"], cam["nx"]), dtype=torch.int32, device=ctx.device)
+        _log(f"trace 37x23 fp32, slice 700, chunks {chunks}")
+        out = ctx.trace(cam, nsteps=ns)
+        torch.cuda.synchronize()
+        long_rays = out["stats"]["long_rays"]
+        _log(f"chunks={chunks}: long rays {long_rays}, longest {int(nso.max())} steps")
+        if expect_long == "none":
+            assert long_rays == 0 and nso.max() > 700
+        else:
+            assert long_rays > 0
+        assert np.array_equal(out["status"].cpu().numpy(), sto)
+        assert np.array_equal(ns.cpu().numpy(), nso)
+        S = out["stokes"].cpu().numpy()
+        assert np.abs(S - ref).max() <= 1e-9 * np.abs(ref[0]).max()
+        _check(S, So, f"37x23 chunks {chunks}")
+    finally:
+        del os.environ["KRT_PATH_CAP"]
+        del os.environ["KRT_CHUNKS"]
+
+
 def test_f32_adaf1024_sampled(ctx):
     """The 1024^2 ADAF bench workload with FP32 transfer: sampled pixels
     against the oracle; the sample's flux and per-pixel errors."""
