@@ -32,6 +32,8 @@ struct krt_ctx {
     // layout-1 snapshots are read through a library-owned layout-0 copy
     void* snap_copy = nullptr;
     size_t snap_copy_bytes = 0;
+    // start values of the MKS inversion for the snapshot's hslope
+    double* x2tab = nullptr;
     int precision = KRT_PRECISION_FP64;
     double* btab = nullptr;
     // wave-synchronous path store
@@ -200,6 +202,7 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
         A.snap.Rlow = d.R_low;
         A.snap.sigma_cut = d.sigma_cut;
         A.snap.rmax = d.r_emit_max;
+        A.snap.x2tab = ctx->x2tab;
     }
     A.adaf.n0 = ctx->adaf.n0_cgs;
     A.adaf.T0 = ctx->adaf.T0_K;
@@ -746,6 +749,7 @@ krt_status krt_destroy(krt_ctx* ctx) {
     if (ctx->tile_order) (void)hipFree(ctx->tile_order);
     if (ctx->probe_dev) (void)hipFree(ctx->probe_dev);
     if (ctx->snap_copy) (void)hipFree(ctx->snap_copy);
+    if (ctx->x2tab) (void)hipFree(ctx->x2tab);
     if (ctx->mlp_P) (void)hipFree(ctx->mlp_P);
     if (ctx->mlp_m) (void)hipFree(ctx->mlp_m);
     if (ctx->mlp_v) (void)hipFree(ctx->mlp_v);
@@ -819,6 +823,14 @@ krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc, c
         KRT_HIP(ctx, hipGetLastError());
         d_prims = ctx->snap_copy;
     }
+    KRT_HIP(ctx, hipSetDevice(ctx->device));
+    if (!ctx->x2tab && hipMalloc(&ctx->x2tab, (kX2Tab + 1) * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->x2tab = nullptr;
+        return fail(ctx, KRT_E_NOMEM, "cannot allocate the MKS inversion table");
+    }
+    hipLaunchKernelGGL(mks_x2_table, dim3((kX2Tab + 128) / 128), dim3(128), 0, ctx->stream, d.hslope, ctx->x2tab);
+    KRT_HIP(ctx, hipGetLastError());
     ctx->snap = d;
     ctx->snap_prims = dtype == KRT_DTYPE_F64 ? static_cast<const double*>(d_prims) : nullptr;
     ctx->snap_prims_f = dtype == KRT_DTYPE_F32 ? static_cast<const float*>(d_prims) : nullptr;

@@ -546,7 +546,25 @@ struct SnapDesc {
     double h, gam;
     double rho_unit, B_unit;   // M_unit / L^3 and c sqrt(4 pi rho_unit)
     double Rhigh, Rlow, sigma_cut, rmax;
+    // x2 at theta = k pi / kX2Tab, k = 0..kX2Tab (the MKS inversion's start
+    // values; null: start from theta / pi)
+    const double* x2tab;
 };
+
+constexpr int kX2Tab = 1024;
+
+// Start value of the MKS inversion x2(theta): linear interpolation in the
+// table (error below 2e-5 for hslope 0.3, which two Newton steps take below
+// the resolution of x2), or theta / pi without a table.
+KRT_HD double x2_start(const double* tab, double th) {
+    if (!tab) return th * (1.0 / kPi);
+    const double u = th * (kX2Tab / kPi);
+    double fi = floor(u);
+    fi = fi >= 0.0 ? (fi > kX2Tab - 1 ? kX2Tab - 1 : fi) : 0.0;   // (NaN: 0)
+    const int i = (int)fi;
+    const double a = tab[i], b = tab[i + 1];
+    return fma(u - fi, b - a, a);
+}
 
 // Trilinear interpolation at grid coordinates; clamped to the end cells in
 // x1 and x2, periodic in x3.
@@ -610,10 +628,10 @@ KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, 
 KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, double th, double ph,
                            const Metric& g, Plasma& p) {
     const double x1 = log_pos(r);
-    double x2 = th * (1.0 / kPi);
+    double x2 = x2_start(s.x2tab, th);
     const double hh = 0.5 * (1.0 - s.h);
-    // Newton from theta/pi: quadratic convergence, at most 8 steps, stopping
-    // once a step no longer moves x2 beyond round-off
+    // Newton from the tabulated start: quadratic convergence, at most 8
+    // steps, stopping once a step no longer moves x2 beyond round-off
     for (int it = 0; it < 8; ++it) {
         double sn, cs;
         sincos_2pi(x2, sn, cs);

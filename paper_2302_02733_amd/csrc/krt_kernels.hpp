@@ -1339,6 +1339,25 @@ __global__ void bessel_table_monomial(double* table) {
     for (int i = 0; i < kBesCoef; ++i) c[i] = a[i];
 }
 
+// MKS inversion table: x2 at theta_k = k pi / kX2Tab for hslope h, each node
+// by Newton from theta_k / pi to convergence (the start values of the
+// per-point inversion in the snapshot model).
+__global__ void mks_x2_table(double h, double* tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > kX2Tab) return;
+    const double th = k * (kPi / kX2Tab);
+    const double hh = 0.5 * (1.0 - h);
+    double x2 = th * (1.0 / kPi);
+    for (int it = 0; it < 64; ++it) {
+        double sn, cs;
+        sincos_2pi(x2, sn, cs);
+        const double dx = (kPi * x2 + hh * sn - th) / (kPi * (1.0 + (1.0 - h) * cs));
+        x2 -= dx;
+        if (fabs(dx) < 1e-16) break;
+    }
+    tab[k] = x2;
+}
+
 // ---------------------------------------------------------------------------
 // Snapshot layout 1 ([8][ncell], one array per field) to layout 0
 // ([ncell][8], the fields of a cell together, which the gather reads as
