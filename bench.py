@@ -36,7 +36,7 @@ if ROOT not in sys.path:
 FLOPS_PER_RAY_STEP = {
     ("adaf", "fp64"): 2570.9,
     ("adaf", "fp32"): 2300.5,
-    ("snapshot", "fp64"): 2406.8,
+    ("snapshot", "fp64"): 2330.2,
     ("snapshot", "fp32"): 2064.8,
 }
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
