@@ -194,6 +194,7 @@ TraceArgs base_args(krt_ctx* ctx, const krt_camera* cam) {
         A.snap.idx1 = 1.0 / d.dx1;   // dx > 0 (checked)
         A.snap.idx2 = 1.0 / d.dx2;
         A.snap.idx3 = 1.0 / d.dx3;
+        A.snap.in3 = 1.0 / d.n3;     // n3 > 0 (checked)
         A.snap.h = d.hslope;
         A.snap.gam = d.gamma_ad;
         A.snap.rho_unit = L > 0.0 ? d.M_unit_g / (L * L * L) : 0.0;

@@ -543,6 +543,7 @@ struct SnapDesc {
     int n1, n2, n3;
     double x1s, dx1, x2s, dx2, x3s, dx3;
     double idx1, idx2, idx3;   // 1 / dx, formed on the host
+    double in3;                // 1 / n3, formed on the host
     double h, gam;
     double rho_unit, B_unit;   // M_unit / L^3 and c sqrt(4 pi rho_unit)
     double Rhigh, Rlow, sigma_cut, rmax;
@@ -587,11 +588,15 @@ KRT_HD void snapshot_interp(const SnapDesc& s, double x1, double x2, double x3, 
     {
         const double X2 = (x3 - s.x3s) * s.idx3 - 0.5;
         const double f = floor(X2);
-        long i = (long)f;
-        const long n = s.n3;
-        i = ((i % n) + n) % n;
-        i0[2] = (int)i;
-        i1[2] = (int)((i + 1) % n);
+        // the cell index f mod n3 in integer-valued FP64 (exact; the
+        // quotient's rounding is corrected by one period) instead of integer
+        // remainders
+        const double n = (double)s.n3;
+        double fi = f - n * floor(f * s.in3);
+        fi = fi < 0.0 ? fi + n : (fi >= n ? fi - n : fi);
+        const int i = (int)fi;
+        i0[2] = i;
+        i1[2] = i + 1 == s.n3 ? 0 : i + 1;
         d[2] = X2 - f;
     }
     for (int q = 0; q < 8; ++q) P[q] = 0.0;
@@ -632,8 +637,9 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     const double hh = 0.5 * (1.0 - s.h);
     // Newton from the tabulated start: quadratic convergence, at most 8
     // steps, stopping once a step no longer moves x2 beyond round-off
+    double cs = 1.0;
     for (int it = 0; it < 8; ++it) {
-        double sn, cs;
+        double sn;
         sincos_2pi(x2, sn, cs);
         const double dx = (kPi * x2 + hh * sn - th) * rcp_fast(kPi * (1.0 + (1.0 - s.h) * cs));
         x2 -= dx;
@@ -643,9 +649,9 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     snapshot_interp(s, x1, x2, ph, P);
     if (!is_finite(P[0] + P[1] + P[2] + P[3] + P[4] + P[5] + P[6] + P[7])) return 2;
     const double rho = P[0], uu = P[1];
-    double s2x, c2x;
-    sincos_2pi(x2, s2x, c2x);
-    const double J2 = kPi * (1.0 + (1.0 - s.h) * c2x);
+    // dtheta/dx2 with the last Newton step's cosine (x2 has moved by less
+    // than 1e-15 since)
+    const double J2 = kPi * (1.0 + (1.0 - s.h) * cs);
     const double U[4] = {0.0, P[2] * r, P[3] * J2, P[4]};
     const double Bv[4] = {0.0, P[5] * r, P[6] * J2, P[7]};
     // g_ij U^i U^j (spatial part)

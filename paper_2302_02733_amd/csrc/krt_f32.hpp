@@ -279,9 +279,11 @@ KRT_HD void snapshot_interp_f(const P* prims, int n1, int n2, int n3, float X0, 
     {
         const float f = floorf(X2);
         int i = (int)f;
-        i = ((i % n3) + n3) % n3;
+        // X2 lies in [0, n3] up to the reduction's rounding: one period
+        // corrects the index
+        i = i < 0 ? i + n3 : (i >= n3 ? i - n3 : i);
         i0[2] = i;
-        i1[2] = (i + 1) % n3;
+        i1[2] = i + 1 == n3 ? 0 : i + 1;
         d[2] = X2 - f;
     }
     for (int q = 0; q < 8; ++q) out[q] = 0.0f;

@@ -607,7 +607,7 @@ KRT_HD void transfer_point_f32(const TraceArgs& A, const PointF& pt, int n, bool
     if (A.model == kModelSnapshot) {
         const SnapDesc& q = A.snap;
         double X2 = ((double)pt.ph - q.x3s) * q.idx3 - 0.5;
-        X2 -= q.n3 * floor(X2 / q.n3);
+        X2 -= q.n3 * floor(X2 * q.in3);
         // no plasma beyond the emission radius (n_e = 0: every coefficient zero)
         if ((double)r <= q.rmax)
             pk = q.prims_f ? snapshot_plasma_f(C, q.prims_f, q.n1, q.n2, q.n3, r, (float)thd, (float)X2, g, p)
