@@ -36,8 +36,8 @@ if ROOT not in sys.path:
 FLOPS_PER_RAY_STEP = {
     ("adaf", "fp64"): 2570.9,
     ("adaf", "fp32"): 2300.5,
-    ("snapshot", "fp64"): 2330.2,
-    ("snapshot", "fp32"): 2064.8,
+    ("snapshot", "fp64"): 2312.0,
+    ("snapshot", "fp32"): 2056.7,
 }
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 
@@ -49,7 +49,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
 # (the FP32-operator mode's FP32 points).
 TRAFFIC_BYTES_PER_RAY_STEP = {
     ("adaf1024", "fp64"): 128.3,
-    ("snap2048", "fp64"): 133.5,
+    ("snap2048", "fp64"): 133.3,
     ("adaf1024", "fp32"): 64.2,
     ("snap2048", "fp32"): 66.2,
 }
