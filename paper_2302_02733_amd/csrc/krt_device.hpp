@@ -649,8 +649,8 @@ KRT_HD int snapshot_plasma(const SnapDesc& s, double a, double m, double r, doub
     snapshot_interp(s, x1, x2, ph, P);
     if (!is_finite(P[0] + P[1] + P[2] + P[3] + P[4] + P[5] + P[6] + P[7])) return 2;
     const double rho = P[0], uu = P[1];
-    // dtheta/dx2 with the last Newton step's cosine (x2 has moved by less
-    // than 1e-15 since)
+    // dtheta/dx2 with the last Newton step's cosine (after the converged
+    // step x2 has moved by less than 1e-15)
     const double J2 = kPi * (1.0 + (1.0 - s.h) * cs);
     const double U[4] = {0.0, P[2] * r, P[3] * J2, P[4]};
     const double Bv[4] = {0.0, P[5] * r, P[6] * J2, P[7]};
