@@ -194,18 +194,23 @@ enum { KRT_DTYPE_F64 = 0, KRT_DTYPE_F32 = 1 };
  * element type KRT_DTYPE_F64 or KRT_DTYPE_F32: the FP32 copy halves the
  * gather traffic and is read by both transfer precisions) is borrowed until
  * the model is replaced or the context is destroyed; the caller must keep it
- * alive and unchanged meanwhile.  Errors: KRT_E_INVAL, KRT_E_UNSUPPORTED
- * (dtype other than KRT_DTYPE_F64 / KRT_DTYPE_F32, layout other than 0 or 1). */
+ * alive and unchanged meanwhile.  The library also builds, on the context's
+ * stream, its table of the MKS inversion x2(theta) for desc's hslope (8 KiB
+ * of device memory it owns).  Errors: KRT_E_INVAL, KRT_E_UNSUPPORTED (dtype
+ * other than KRT_DTYPE_F64 / KRT_DTYPE_F32, layout other than 0 or 1),
+ * KRT_E_NOMEM (the table or a layout-1 copy cannot be allocated). */
 krt_status krt_set_model_snapshot(krt_ctx* ctx, const krt_snapshot_desc* desc,
                                   const void* d_prims, int dtype);
 
 /* Arithmetic of the polarized transfer (Sec. 4 of the paper names single
  * precision as the next speed-up).  KRT_PRECISION_FP64 (default): everything
- * FP64.  KRT_PRECISION_FP32_TRANSFER: geodesics, their step control and the
- * stored path stay FP64; the operators of each transfer step (metric and
- * connection, plasma, coefficients, fluid tetrad, propagator) are FP32, while
- * the coherency matrix and the transport state stay FP64 and every increment
- * is added in FP64.  Applies to later krt_trace calls.  Errors: KRT_E_INVAL. */
+ * FP64.  KRT_PRECISION_FP32_TRANSFER: geodesics and their step control stay
+ * FP64; the stored path is kept in FP32 (32 B per point: r, the signed
+ * distance to the nearer pole, phi reduced to [0, 2 pi), K^mu, the step); the
+ * operators of each transfer step (metric and connection, plasma,
+ * coefficients, fluid tetrad, propagator) are FP32, while the coherency
+ * matrix and the transport state stay FP64 and every increment is added in
+ * FP64.  Applies to later krt_trace calls.  Errors: KRT_E_INVAL. */
 enum { KRT_PRECISION_FP64 = 0, KRT_PRECISION_FP32_TRANSFER = 1 };
 krt_status krt_set_precision(krt_ctx* ctx, int precision);
 
