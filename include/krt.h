@@ -53,7 +53,7 @@ typedef enum {
     KRT_E_NOMEM = 2,       /* device or host allocation failed                */
     KRT_E_HIP = 3,         /* HIP runtime error                               */
     KRT_E_STATE = 4,       /* call out of order (e.g. no model set)           */
-    KRT_E_UNSUPPORTED = 5  /* valid but not supported by this build           */
+    KRT_E_UNSUPPORTED = 5  /* valid but not supported by this library         */
 } krt_status;
 
 /* Per-pixel ray status (uint8 status image). */

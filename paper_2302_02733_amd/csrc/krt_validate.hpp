@@ -59,7 +59,7 @@ inline std::string check_units(const krt_units* u) {
     return "";
 }
 
-// ADAF parameters; *unsupported is set for valid values this build does not
+// ADAF parameters; *unsupported is set for valid values the library does not
 // implement.
 inline std::string check_adaf(const krt_adaf* p, bool* unsupported) {
     *unsupported = false;
